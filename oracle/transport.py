@@ -1,0 +1,476 @@
+"""FP64 CPU oracle of the implicit MGFLD transport step (test infrastructure only).
+
+Notation follows the paper (CHIMERA, arXiv 1809.05608):
+  psi      zeroth angular moment psi^(0) of the occupation (dimensionless)
+  H        first moment psi^(1) at a zone edge (the flux, eq. a59)
+  lambda   transport mean free path (eq. a17), 1/lambda = kappa_a + eta + kappa_s
+           (absorption plus emission inverse mean free paths, eq. d10, plus the
+           isoenergetic scattering opacity, eq. d8c)
+  F        flux limiter F_intrp (eq. a20)
+  V_i, A   zone volume and edge area with the common 4*pi dropped and Gamma = 1
+  eps_k    group-centre energies (eq. a01), W_k = eps_k^2 d eps_k (eq. a01b)
+The lapse a is 1 (no lapse input), so E = eps (eq. a8a).
+
+One "system" is one (species, ray): I radial zones x N energy groups.  The
+unknowns are psi^{n+1}_{i,k}; the residual is c*dt times eq. a58 with the
+source of eq. a54 (emission/absorption with Pauli blocking) and the zeroth
+moment of eq. d8 / eq. d40 (inelastic NES-like scattering, Phi_0 terms).
+
+Readings where the paper is silent or garbled (each is listed in the design doc):
+  * eq. a01 prints eps_k instead of eps_k^2 on the left; the square is restored
+    so that eq. a01b holds.
+  * the limiter's psi in eq. a20 is the edge mean (psi_i + psi_{i+1})/2, floored
+    at psi_floor; |d psi/dR| uses the same one-sided difference as eq. a59.
+  * only F_intrp is used (F_geom needs a neutrinosphere radius, eq. a23-a26a).
+  * the outer boundary is free streaming, psi^(1) = psi^(0) of the last zone
+    (the limit of eq. a22), or zero flux; the inner boundary has zero flux.
+  * NES enters moment 0 through the Phi_0 terms only and is excluded from the
+    transport opacity, so the off-diagonal radial blocks stay diagonal (eq. a62ae).
+  * the NES kernel obeys the in/out symmetry (eq. d3) in the weighted discrete
+    form W_k K^in_{kk'} = W_k' K^out_{k'k} and detailed balance (eq. d4), with the
+    directly computed part carrying a min(1, e^{-x}) factor.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg
+
+EPS0_MEV = 10.0          # NES reference energy (kernel scale eps_k eps_k' / eps0^2)
+C_LIGHT = 2.99792458e10  # cm/s, used only for the luminosity (number per unit time)
+
+TERM_DIFFUSION = 1
+TERM_EMABS = 2
+TERM_NES = 4
+
+
+@dataclasses.dataclass
+class System:
+    """Inputs of one (species, ray) system, all float64 numpy arrays."""
+    r_edge: np.ndarray      # [I+1] cm
+    e_edge: np.ndarray      # [N+1] MeV
+    temp: np.ndarray        # [I] MeV
+    kappa_a: np.ndarray     # [I][N] cm^-1
+    eta: np.ndarray         # [I][N] cm^-1 (emissivity j)
+    kappa_s: np.ndarray     # [I][N] cm^-1
+    nes_amp: np.ndarray     # [I] cm^-1
+    nes_g: np.ndarray       # [N][N]
+    c_dt: float             # cm
+    inner_bc: int = 0
+    outer_bc: int = 1
+    terms: int = 7
+    limiter: int = 1
+    psi_floor: float = 1e-300
+
+    @property
+    def I(self) -> int:
+        return self.kappa_a.shape[0]
+
+    @property
+    def N(self) -> int:
+        return self.kappa_a.shape[1]
+
+
+def systems_from_workload(w: dict) -> List[List[System]]:
+    """Split workload arrays (layouts [S][R][I][N], [R][I], [S][R][I]) into systems[s][r]."""
+    out = []
+    for s in range(w["S"]):
+        row = []
+        for r in range(w["R"]):
+            row.append(System(
+                r_edge=w["r_edge"][r], e_edge=w["e_edge"], temp=w["temp"][r],
+                kappa_a=w["kappa_a"][s, r], eta=w["eta"][s, r], kappa_s=w["kappa_s"][s, r],
+                nes_amp=w["nes_amp"][s, r], nes_g=w["nes_g"], c_dt=w["c_dt"],
+                inner_bc=w["inner_bc"], outer_bc=w["outer_bc"], terms=w["terms"],
+                limiter=w["limiter"], psi_floor=w["psi_floor"]))
+        out.append(row)
+    return out
+
+
+# ---------------------------------------------------------------- grids
+
+def group_energies(e_edge: np.ndarray):
+    """Group centres eps_k (eq. a01 with eps_k^2 on the left) and weights W_k (eq. a01b)."""
+    lo, hi = e_edge[:-1], e_edge[1:]
+    eps = np.sqrt((hi ** 2 + hi * lo + lo ** 2) / 3.0)
+    W = (hi ** 3 - lo ** 3) / 3.0
+    return eps, W
+
+
+def geometry(r_edge: np.ndarray):
+    """Zone centres R_i, volumes V_i, edge areas A_{i+1/2}, centre distances D_{i+1/2}.
+
+    Definitions stated after eq. a59: R_i is the mean of its edges, V_i the shell
+    volume and A the edge area, the common 4*pi dropped and Gamma = 1.
+    Returns R [I], V [I], A [I+1] (edge 0 is the inner edge), D [I-1] (interior edges).
+    """
+    Rc = 0.5 * (r_edge[:-1] + r_edge[1:])
+    V = (r_edge[1:] ** 3 - r_edge[:-1] ** 3) / 3.0
+    A = r_edge ** 2
+    D = Rc[1:] - Rc[:-1]
+    return Rc, V, A, D
+
+
+# ---------------------------------------------------------------- physics pieces
+
+def nes_kernels(amp: float, T: float, eps: np.ndarray, W: np.ndarray, G: np.ndarray):
+    """Out/in NES kernels K^out_{kk'}, K^in_{kk'} of one zone (Phi_0 terms of eq. d8).
+
+    K^out_{kk'} = amp (eps_k eps_k'/eps0^2) G_{kk'} (W_k'/Wbar) min(1, exp(-(eps_k' - eps_k)/T))
+    K^in_{kk'}  = amp (eps_k eps_k'/eps0^2) G_{kk'} (W_k'/Wbar) min(1, exp(+(eps_k' - eps_k)/T))
+    so that K^in/K^out = exp((eps_k' - eps_k)/T) (detailed balance, eq. d4) and
+    W_k K^in_{kk'} = W_k' K^out_{k'k} (in/out symmetry, eq. d3, with the phase-space
+    weight of the discrete sum of eq. d40).
+    """
+    Wbar = W.mean()
+    base = amp * np.outer(eps, eps) / EPS0_MEV ** 2 * G * (W / Wbar)[None, :]
+    x = (eps[None, :] - eps[:, None]) / T          # (eps_k' - eps_k)/T, row k, column k'
+    k_out = base * np.exp(np.minimum(-x, 0.0))     # min(1, e^{-x})
+    k_in = base * np.exp(np.minimum(x, 0.0))       # min(1, e^{+x})
+    return k_out, k_in
+
+
+def edge_flux(u, v, lam, D, floor, limiter=1):
+    """Flux H = psi^(1) at an interior edge and its partial derivatives.
+
+    eq. a59 with the limiter of eq. a20 (Gamma = 1):
+        H = -(lam/3) F (v - u)/D,   F = [1 + lam |v - u| / (3 D m)]^{-1},
+        m = max((u + v)/2, floor)
+    i.e. H = -lam m (v - u) / (3 D m + lam |v - u|).  With limiter=0, F = 1.
+    Returns H, dH/du, dH/dv, dH/dlam (arrays over groups).
+    """
+    delta = v - u
+    if limiter == 0:
+        H = -lam * delta / (3.0 * D)
+        dH_dd = -lam / (3.0 * D)
+        return H, -dH_dd, dH_dd, -delta / (3.0 * D)
+    mean = 0.5 * (u + v)
+    m = np.maximum(mean, floor)
+    above = (mean > floor).astype(np.float64)
+    den = 3.0 * D * m + lam * np.abs(delta)
+    r = m / den
+    q = delta / den
+    H = -lam * delta * r
+    dH_ddelta = -3.0 * D * lam * r * r            # d/d(delta) at fixed m
+    dH_dm = -lam * lam * q * np.abs(q) * above     # d/dm at fixed delta
+    dH_du = -dH_ddelta + 0.5 * dH_dm
+    dH_dv = dH_ddelta + 0.5 * dH_dm
+    dH_dlam = -3.0 * D * delta * r * r
+    return H, dH_du, dH_dv, dH_dlam
+
+
+def _lambda(sys: System):
+    return 1.0 / (sys.kappa_a + sys.eta + sys.kappa_s)
+
+
+def _edge_fluxes(sys: System, psi: np.ndarray):
+    """H at all I+1 edges [I+1][N] plus derivatives at interior edges."""
+    I, N = psi.shape
+    _, _, _, D = geometry(sys.r_edge)
+    lam = _lambda(sys)
+    H = np.zeros((I + 1, N))
+    dHu = np.zeros((I + 1, N))
+    dHv = np.zeros((I + 1, N))
+    dHl = np.zeros((I + 1, N))
+    lam_e = np.zeros((I + 1, N))
+    for e in range(1, I):                            # edge e = i + 1/2 between zones e-1 and e
+        lam_e[e] = np.sqrt(lam[e - 1] * lam[e])     # geometric mean, stated after eq. a59
+        H[e], dHu[e], dHv[e], dHl[e] = edge_flux(psi[e - 1], psi[e], lam_e[e], D[e - 1],
+                                                 sys.psi_floor, sys.limiter)
+    # inner boundary: zero flux (H[0] = 0).  Outer boundary:
+    if sys.outer_bc == 1:
+        H[I] = psi[I - 1]                            # free streaming, psi^(1) = psi^(0)
+        dHu[I] = 1.0
+    return H, dHu, dHv, dHl, lam_e
+
+
+def nes_source(sys: System, psi: np.ndarray, unit_amplitude: bool = False):
+    """S_{i,k}: zeroth moment of the NES collision term (eq. d8, Phi_0 terms; eq. d40)."""
+    I, N = psi.shape
+    eps, W = group_energies(sys.e_edge)
+    S = np.zeros((I, N))
+    for i in range(I):
+        amp = 1.0 if unit_amplitude else sys.nes_amp[i]
+        k_out, k_in = nes_kernels(amp, sys.temp[i], eps, W, sys.nes_g)
+        p = psi[i]
+        S[i] = (1.0 - p) * (k_in @ p) - p * (k_out @ (1.0 - p))
+    return S
+
+
+# ---------------------------------------------------------------- residual and Jacobian
+
+def residual(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """G(psi) = c*dt times eq. a58 (lapse 1), per cell [I][N].
+
+    G_{i,k} = psi - psi^n + c dt { (A_{i+1/2} H_{i+1/2} - A_{i-1/2} H_{i-1/2}) / V_i
+                                   - eta (1 - psi) + kappa_a psi - S_{i,k} }
+    """
+    _, V, A, _ = geometry(sys.r_edge)
+    G = psi - psi_n
+    if sys.terms & TERM_DIFFUSION:
+        H = _edge_fluxes(sys, psi)[0]
+        G = G + sys.c_dt * (A[1:, None] * H[1:] - A[:-1, None] * H[:-1]) / V[:, None]
+    if sys.terms & TERM_EMABS:
+        G = G + sys.c_dt * (-sys.eta * (1.0 - psi) + sys.kappa_a * psi)
+    if sys.terms & TERM_NES:
+        G = G - sys.c_dt * nes_source(sys, psi)
+    return G
+
+
+def jacobian_blocks(sys: System, psi: np.ndarray):
+    """Exact Jacobian of G in block-tridiagonal form (eq. a62ae).
+
+    Returns A [I][N][N] (dense diagonal blocks), bm [I][N], bp [I][N] (the diagonal
+    off-diagonal blocks coupling zone i to zones i-1 and i+1).
+    """
+    I, N = psi.shape
+    _, V, Aed, _ = geometry(sys.r_edge)
+    eps, W = group_energies(sys.e_edge)
+    c = sys.c_dt
+    blocks = np.zeros((I, N, N))
+    bm = np.zeros((I, N))
+    bp = np.zeros((I, N))
+    diag = np.ones((I, N))
+    if sys.terms & TERM_DIFFUSION:
+        _, dHu, dHv, _, _ = _edge_fluxes(sys, psi)
+        for i in range(I):
+            # G_i contains +A_{i+1/2} H_{i+1/2}(psi_i, psi_{i+1}) - A_{i-1/2} H_{i-1/2}(psi_{i-1}, psi_i)
+            diag[i] += c * (Aed[i + 1] * dHu[i + 1] - Aed[i] * dHv[i]) / V[i]
+            if i + 1 < I:
+                bp[i] = c * Aed[i + 1] * dHv[i + 1] / V[i]
+            if i > 0:
+                bm[i] = -c * Aed[i] * dHu[i] / V[i]
+    if sys.terms & TERM_EMABS:
+        diag += c * (sys.eta + sys.kappa_a)
+    for i in range(I):
+        blocks[i][np.diag_indices(N)] = diag[i]
+        if sys.terms & TERM_NES:
+            k_out, k_in = nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g)
+            p = psi[i]
+            # -c dS_k/dpsi_m : dense part for every m (the m = k term included) ...
+            blocks[i] -= c * ((1.0 - p)[:, None] * k_in + p[:, None] * k_out)
+            # ... plus the diagonal derivative through the explicit (1 - psi_k), psi_k factors
+            blocks[i][np.diag_indices(N)] += c * (k_in @ p + k_out @ (1.0 - p))
+    return blocks, bm, bp
+
+
+def dense_jacobian(sys: System, psi: np.ndarray) -> np.ndarray:
+    """The full (I*N) x (I*N) Jacobian, row/column index i*N + k."""
+    blocks, bm, bp = jacobian_blocks(sys, psi)
+    I, N = psi.shape
+    J = np.zeros((I * N, I * N))
+    for i in range(I):
+        J[i * N:(i + 1) * N, i * N:(i + 1) * N] = blocks[i]
+        if i > 0:
+            J[i * N:(i + 1) * N, (i - 1) * N:i * N] = np.diag(bm[i])
+        if i + 1 < I:
+            J[i * N:(i + 1) * N, (i + 1) * N:(i + 2) * N] = np.diag(bp[i])
+    return J
+
+
+# ---------------------------------------------------------------- linear solves
+
+def block_thomas_solve(blocks, bm, bp, rhs, transpose: bool = False):
+    """Solve J x = rhs (or J^T x = rhs) by block-Thomas elimination.
+
+    Forward sweep: Ahat_i = A_i - diag(bm_i) C_{i-1}, y_i = Ahat_i^{-1}(rhs_i - bm_i * y_{i-1}),
+    C_i = Ahat_i^{-1} diag(bp_i), each Ahat_i factored by LU with partial pivoting.
+    Back substitution: x_{I-1} = y_{I-1}, x_i = y_i - C_i x_{i+1}.
+    J^T has blocks A_i^T and off-diagonals bp_{i-1} (below) and bm_{i+1} (above).
+    """
+    I, N = rhs.shape
+    if transpose:
+        blocks = np.transpose(blocks, (0, 2, 1))
+        lower = np.zeros_like(bm)
+        upper = np.zeros_like(bp)
+        lower[1:] = bp[:-1]
+        upper[:-1] = bm[1:]
+        bm, bp = lower, upper
+    C = np.zeros((I, N, N))
+    y = np.zeros((I, N))
+    for i in range(I):
+        Ahat = blocks[i].copy()
+        g = rhs[i].copy()
+        if i > 0:
+            Ahat -= bm[i][:, None] * C[i - 1]
+            g -= bm[i] * y[i - 1]
+        lu = scipy.linalg.lu_factor(Ahat)
+        y[i] = scipy.linalg.lu_solve(lu, g)
+        C[i] = scipy.linalg.lu_solve(lu, np.diag(bp[i]))
+    x = np.zeros((I, N))
+    x[I - 1] = y[I - 1]
+    for i in range(I - 2, -1, -1):
+        x[i] = y[i] - C[i] @ x[i + 1]
+    return x
+
+
+def dense_solve(sys: System, psi: np.ndarray, rhs: np.ndarray, transpose: bool = False):
+    """Second, independent route: assemble the dense J and call LAPACK (numpy.linalg.solve)."""
+    J = dense_jacobian(sys, psi)
+    if transpose:
+        J = J.T
+    return np.linalg.solve(J, rhs.reshape(-1)).reshape(rhs.shape)
+
+
+# ---------------------------------------------------------------- Newton iteration
+
+@dataclasses.dataclass
+class NewtonResult:
+    psi: np.ndarray
+    iters: int
+    res0: float
+    res: float
+    converged: bool
+    history: list
+
+
+def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
+           max_iter: int = 30, rtol: float = 0.0) -> NewtonResult:
+    """Backward-Euler Newton iteration (eq. a62aa) for psi^{n+1} of one system.
+
+    Starts from psi0 (default psi^n).  Before each update the residual norm
+    r_m = max|G(psi^(m))| is compared with rtol * r_0; the iteration stops when
+    r_m <= rtol * r_0 or after max_iter updates.  Each update solves J delta = -G.
+    """
+    psi = (psi_n if psi0 is None else psi0).copy()
+    hist = []
+    res0 = None
+    iters = 0
+    for _ in range(max_iter):
+        G = residual(sys, psi_n, psi)
+        r = float(np.max(np.abs(G)))
+        hist.append(r)
+        if res0 is None:
+            res0 = r
+        if r <= rtol * res0:
+            break
+        blocks, bm, bp = jacobian_blocks(sys, psi)
+        psi = psi + block_thomas_solve(blocks, bm, bp, -G)
+        iters += 1
+    G = residual(sys, psi_n, psi)
+    r = float(np.max(np.abs(G)))
+    if res0 is None:
+        res0 = r
+    hist.append(r)
+    return NewtonResult(psi=psi, iters=iters, res0=res0, res=r, converged=bool(r <= rtol * res0), history=hist)
+
+
+# ---------------------------------------------------------------- conservation sums and luminosity
+
+def step_stats(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> dict:
+    """FP64 sums of one system (number conservation, eqs. a60-a62).
+
+    n_tot   = sum_i V_i sum_k W_k psi_{i,k}         (neutrino number, constants dropped)
+    e_tot   = sum_i V_i sum_k W_k eps_k psi_{i,k}   (energy)
+    q_n     = c dt sum V W [eta (1 - psi) - kappa_a psi]   (emission minus absorption)
+    nes_n   = c dt sum V W S                          (NES number source, zero by eq. d3)
+    b_n     = c dt A_{I+1/2} sum_k W_k H_{I+1/2,k}     (number through the outer surface)
+    budget  = n_tot - n_tot^n + b_n - q_n - nes_n    (equals sum V W G)
+    lum_n   = c A_{I+1/2} sum_k W_k H_{I+1/2,k}        (number luminosity, 4pi and (hc)^-3 dropped)
+    """
+    _, V, A, _ = geometry(sys.r_edge)
+    eps, W = group_energies(sys.e_edge)
+    I, N = psi.shape
+    VW = V[:, None] * W[None, :]
+    n_tot = float(np.sum(VW * psi))
+    n_old = float(np.sum(VW * psi_n))
+    e_tot = float(np.sum(VW * eps[None, :] * psi))
+    q_n = float(sys.c_dt * np.sum(VW * (sys.eta * (1.0 - psi) - sys.kappa_a * psi))) if sys.terms & TERM_EMABS else 0.0
+    nes_n = float(sys.c_dt * np.sum(VW * nes_source(sys, psi))) if sys.terms & TERM_NES else 0.0
+    if sys.terms & TERM_DIFFUSION and sys.outer_bc == 1:
+        h_out = psi[I - 1]
+    else:
+        h_out = np.zeros(N)
+    b_n = float(sys.c_dt * A[I] * np.sum(W * h_out))
+    return dict(n_tot=n_tot, e_tot=e_tot, q_n=q_n, nes_n=nes_n, b_n=b_n,
+                budget=n_tot - n_old + b_n - q_n - nes_n,
+                lum_n=float(C_LIGHT * A[I] * np.sum(W * h_out)))
+
+
+def luminosity(sys: System, psi: np.ndarray) -> float:
+    """L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}: number leaving the outer surface per unit time (eq. a62)."""
+    _, _, A, _ = geometry(sys.r_edge)
+    _, W = group_energies(sys.e_edge)
+    I = psi.shape[0]
+    if not (sys.terms & TERM_DIFFUSION) or sys.outer_bc != 1:
+        return 0.0
+    return float(C_LIGHT * A[I] * np.sum(W * psi[I - 1]))
+
+
+def luminosity_seed(sys: System, shape) -> np.ndarray:
+    """dL_N/dpsi as a cell array: nonzero only in the outermost zone."""
+    _, _, A, _ = geometry(sys.r_edge)
+    _, W = group_energies(sys.e_edge)
+    I, N = shape
+    seed = np.zeros((I, N))
+    if (sys.terms & TERM_DIFFUSION) and sys.outer_bc == 1:
+        seed[I - 1] = C_LIGHT * A[I] * W
+    return seed
+
+
+# ---------------------------------------------------------------- adjoint
+
+def adjoint(sys: System, psi: np.ndarray, seed: np.ndarray) -> np.ndarray:
+    """mu solving J(psi)^T mu = seed through the dense transpose (numpy.linalg.solve)."""
+    return dense_solve(sys, psi, seed, transpose=True)
+
+
+def param_vjp(sys: System, psi: np.ndarray, mu: np.ndarray) -> dict:
+    """-mu^T dG/dtheta for theta in (kappa_a, eta, kappa_s, nes_amp, psi_n).
+
+    dG/dkappa_a = c dt psi and dG/deta = -c dt (1 - psi) on the own cell (eq. a54 form);
+    all three opacities also reach G_{i-1}, G_i, G_{i+1} through lambda_i, the edge
+    means lambda_{i+-1/2} = sqrt(lambda_i lambda_{i+-1}) and the edge fluxes (eq. a59),
+    with d lambda_e / d chi_i = -lambda_e lambda_i / 2 for chi = 1/lambda;
+    dG/d amp_i = -c dt S_{i,k}/amp_i; dG/dpsi^n = -1.
+    """
+    I, N = psi.shape
+    _, V, A, _ = geometry(sys.r_edge)
+    c = sys.c_dt
+    lam = _lambda(sys)
+    g_chi = np.zeros((I, N))      # mu-weighted dG/dchi_i through the edge fluxes
+    if sys.terms & TERM_DIFFUSION:
+        _, _, _, dHl, lam_e = _edge_fluxes(sys, psi)
+        for e in range(1, I):          # interior edge between zones e-1 and e
+            # G_{e-1} += c A_e H_e / V_{e-1};  G_e -= c A_e H_e / V_e
+            w = c * A[e] * (mu[e - 1] / V[e - 1] - mu[e] / V[e])     # mu-weighted dG/dH_e
+            for zone in (e - 1, e):
+                dlam_dchi = -0.5 * lam_e[e] * lam[zone]
+                g_chi[zone] += w * dHl[e] * dlam_dchi
+    g_ka = g_chi.copy()
+    g_eta = g_chi.copy()
+    g_ks = g_chi.copy()
+    if sys.terms & TERM_EMABS:
+        g_ka += mu * c * psi
+        g_eta += mu * (-c * (1.0 - psi))
+    g_amp = np.zeros(I)
+    if sys.terms & TERM_NES:
+        S1 = nes_source(sys, psi, unit_amplitude=True)
+        g_amp = np.sum(mu * (-c * S1), axis=1)
+    return dict(kappa_a=-g_ka, eta=-g_eta, kappa_s=-g_ks, nes_amp=-g_amp, psi_n=mu.copy())
+
+
+# ---------------------------------------------------------------- batch helpers
+
+def newton_batch(w: dict, max_iter: int, rtol: float, systems=None):
+    """Run `newton` on (s, r) systems of a workload dict; returns psi [S][R][I][N] and per-system info."""
+    syss = systems_from_workload(w)
+    psi = np.array(w["psi_n"], copy=True)
+    info = {}
+    pairs = systems if systems is not None else [(s, r) for s in range(w["S"]) for r in range(w["R"])]
+    for s, r in pairs:
+        res = newton(syss[s][r], w["psi_n"][s, r], max_iter=max_iter, rtol=rtol)
+        psi[s, r] = res.psi
+        info[(s, r)] = res
+    return psi, info
+
+
+def residual_batch(w: dict, psi: np.ndarray) -> np.ndarray:
+    syss = systems_from_workload(w)
+    G = np.zeros_like(psi)
+    for s in range(w["S"]):
+        for r in range(w["R"]):
+            G[s, r] = residual(syss[s][r], w["psi_n"][s, r], psi[s, r])
+    return G

@@ -1,0 +1,10 @@
+"""Seeded synthetic inputs for the ray-by-ray MGFLD transport step.
+
+This package defines workloads only (grids, stellar profiles, opacities).  It
+contains no transport arithmetic, and both the CPU oracle and the HIP path
+consume the arrays it produces.
+"""
+from .workload import (  # noqa: F401
+    C_LIGHT, SEED, TERM_DIFFUSION, TERM_EMABS, TERM_NES, TERMS_ALL,
+    BC_ZERO_FLUX, BC_FREE_STREAM, CONFIGS, Workload, make, make_custom,
+)

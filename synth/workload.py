@@ -1,0 +1,267 @@
+"""Synthetic stellar-profile workloads for the implicit MGFLD transport step.
+
+The paper's production runs use progenitor models and tabulated opacities that
+are not available here, so every input is a seeded analytic stand-in with the
+paper's production shapes: 20 energy groups, 4 species, about 540 radial zones
+(Transport Sources section; Code Comparison section; the 540x180x180 3-D grid of
+the hydrodynamics tests).
+
+Recipe (one workload = S species x R rays x I zones x N groups):
+
+* radial zone edges log-spaced from 1e6 cm to 1e9 cm; zone centres are edge means;
+* energy-group edges log-spaced from 2 MeV to 300 MeV; opacities are evaluated at
+  the group centre energy whose square is the mean of e_lo^2, e_lo*e_hi, e_hi^2
+  (the zone-centre definition of the paper's energy grid, eq. a01 with the
+  square restored, which keeps eq. a01b exact);
+* rho(r) = max(1e14 (r/1e6)^-3 * exp(0.1 z_rho), 1e6) g/cm^3 and
+  T(r) = 30 (r/1e6)^-0.7 * exp(0.1 z_T) MeV, with one standard-normal draw per ray
+  and per quantity (a lognormal ray-to-ray perturbation with sigma 0.1);
+* chemical potential mu = +2T for nu_e and nu_x, -2T for the antineutrinos;
+* absorption opacity kappa_a = 1e-6 (rho/1e14) (eps/10 MeV)^2 cm^-1;
+  emissivity from detailed balance with Fermi-Dirac, eta = f_s kappa_a exp(-(eps-mu)/T)
+  with f_s = 0.5 for the heavy-lepton species; isoenergetic scattering kappa_s = 2 kappa_a;
+* NES-like kernel: amplitude a = 1e-7 (rho/1e14) cm^-1 per zone and a symmetric
+  Gaussian G[k][k'] = exp(-(ln eps_k - ln eps_k')^2 / (2 * 0.3^2));
+* initial state psi^n = 0.9 f_FD(eps; mu, T);
+* c*dt with dt = 1e-6 s.
+
+Extras per configuration: opacity spikes on 5% of the rays (stress case) and a
+smooth 1% per-step drift of rho and T (multi-step case).
+
+No array here is computed by the transport method: the oracle and the device
+path both take these arrays as given inputs.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+C_LIGHT = 2.99792458e10          # cm/s
+SEED = 180905608
+DT = 1.0e-6                      # s
+
+TERM_DIFFUSION = 1
+TERM_EMABS = 2
+TERM_NES = 4
+TERMS_ALL = TERM_DIFFUSION | TERM_EMABS | TERM_NES
+
+BC_ZERO_FLUX = 0
+BC_FREE_STREAM = 1
+
+# name, rays, zones, groups, species
+CONFIGS = {
+    0: dict(name="fp64-16r-64z-12g-1s", R=16, I=64, N=12, S=1),
+    1: dict(name="fp64-180r-540z-20g-4s", R=180, I=540, N=20, S=4),
+    2: dict(name="mixed-4096r-540z-20g-4s-spikes", R=4096, I=540, N=20, S=4),
+    3: dict(name="adjoint-1024r-540z-20g-1s", R=1024, I=540, N=20, S=1),
+    4: dict(name="multistep-16384r-540z-20g-4s", R=16384, I=540, N=20, S=4),
+}
+
+N_SPIKE_FRACTION = 0.05
+SPIKE_HALF_WIDTH = 8             # 17 zones
+DRIFT_AMPLITUDE = 0.01
+
+
+@dataclasses.dataclass
+class Workload:
+    """One batch of independent (species, ray) systems, all arrays float64.
+
+    Layouts: cell arrays [S][R][I][N] (group fastest), zone arrays [R][I],
+    per-system-zone arrays [S][R][I], radial edges [R][I+1], energy edges [N+1],
+    NES shape matrix [N][N].
+    """
+    name: str
+    S: int
+    R: int
+    I: int
+    N: int
+    c_dt: float
+    r_edge: torch.Tensor
+    e_edge: torch.Tensor
+    temp: torch.Tensor
+    kappa_a: torch.Tensor
+    eta: torch.Tensor
+    kappa_s: torch.Tensor
+    psi_n: torch.Tensor
+    nes_amp: torch.Tensor
+    nes_g: torch.Tensor
+    inner_bc: int = BC_ZERO_FLUX
+    outer_bc: int = BC_FREE_STREAM
+    terms: int = TERMS_ALL
+    limiter: int = 1
+    psi_floor: float = 1e-300
+
+    @property
+    def n_systems(self) -> int:
+        return self.S * self.R
+
+    @property
+    def n_cells(self) -> int:
+        return self.S * self.R * self.I * self.N
+
+    def tensors(self):
+        return dict(r_edge=self.r_edge, e_edge=self.e_edge, temp=self.temp,
+                    kappa_a=self.kappa_a, eta=self.eta, kappa_s=self.kappa_s,
+                    psi_n=self.psi_n, nes_amp=self.nes_amp, nes_g=self.nes_g)
+
+    def to(self, device) -> "Workload":
+        kw = {k: v.to(device).contiguous() for k, v in self.tensors().items()}
+        return dataclasses.replace(self, **kw)
+
+    def numpy(self) -> dict:
+        """All arrays as contiguous float64 numpy arrays plus the scalars."""
+        out = {k: np.ascontiguousarray(v.detach().cpu().numpy()) for k, v in self.tensors().items()}
+        out.update(S=self.S, R=self.R, I=self.I, N=self.N, c_dt=self.c_dt,
+                   inner_bc=self.inner_bc, outer_bc=self.outer_bc, terms=self.terms,
+                   limiter=self.limiter, psi_floor=self.psi_floor)
+        return out
+
+    def select_rays(self, rays: Sequence[int]) -> "Workload":
+        idx = torch.as_tensor(list(rays), dtype=torch.long, device=self.r_edge.device)
+        return dataclasses.replace(
+            self, R=len(rays),
+            r_edge=self.r_edge.index_select(0, idx).contiguous(),
+            temp=self.temp.index_select(0, idx).contiguous(),
+            kappa_a=self.kappa_a.index_select(1, idx).contiguous(),
+            eta=self.eta.index_select(1, idx).contiguous(),
+            kappa_s=self.kappa_s.index_select(1, idx).contiguous(),
+            psi_n=self.psi_n.index_select(1, idx).contiguous(),
+            nes_amp=self.nes_amp.index_select(1, idx).contiguous())
+
+
+def _rng(cfg: int, *extra: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(SEED, spawn_key=(cfg,) + extra)))
+
+
+def _group_energies(e_edge: torch.Tensor) -> torch.Tensor:
+    lo, hi = e_edge[:-1], e_edge[1:]
+    return torch.sqrt((hi * hi + hi * lo + lo * lo) / 3.0)
+
+
+def _fermi_dirac(x: torch.Tensor) -> torch.Tensor:
+    """1/(1+e^x) evaluated without overflow (e^-x/(1+e^-x) for x > 0)."""
+    e = torch.exp(-x.abs())
+    return torch.where(x > 0, e / (1.0 + e), 1.0 / (1.0 + e))
+
+
+def _species_sign_weight(S: int):
+    sign = [1.0, -1.0, 1.0, -1.0][:S]
+    weight = [1.0, 1.0, 0.5, 0.5][:S]
+    return sign, weight
+
+
+def _profiles(cfg: int, R_full: int, I: int, rays: np.ndarray, step: int):
+    """rho [R][I], T [R][I], r_edge [I+1] for the selected rays (numpy, float64)."""
+    rng = _rng(cfg)
+    z_rho = rng.standard_normal(R_full)
+    z_T = rng.standard_normal(R_full)
+    r_edge = 1e6 * 1000.0 ** (np.arange(I + 1, dtype=np.float64) / I)
+    r_c = 0.5 * (r_edge[1:] + r_edge[:-1])
+    x = r_c / 1e6
+    rho = 1e14 * x[None, :] ** -3.0 * np.exp(0.1 * z_rho[rays])[:, None]
+    T = 30.0 * x[None, :] ** -0.7 * np.exp(0.1 * z_T[rays])[:, None]
+    rho = np.maximum(rho, 1e6)
+    if step > 0:
+        # smooth 1% drift per step, an independent phase per (ray, step) and quantity
+        phase_arg = 2.0 * math.pi * np.log(x) / math.log(1000.0)
+        for s in range(1, step + 1):
+            drng = _rng(cfg, 2, s)
+            ph_rho = drng.uniform(0.0, 2.0 * math.pi, R_full)[rays]
+            ph_T = drng.uniform(0.0, 2.0 * math.pi, R_full)[rays]
+            rho = rho * (1.0 + DRIFT_AMPLITUDE * np.sin(phase_arg[None, :] + ph_rho[:, None]))
+            T = T * (1.0 + DRIFT_AMPLITUDE * np.sin(phase_arg[None, :] + ph_T[:, None]))
+            rho = np.maximum(rho, 1e6)
+    return rho, T, r_edge
+
+
+def _spikes(cfg: int, R_full: int, I: int):
+    """(ray ids, centre zones, multiplicative factors) of the opacity spikes."""
+    rng = _rng(cfg)
+    rng.standard_normal(R_full)
+    rng.standard_normal(R_full)
+    n = int(round(N_SPIKE_FRACTION * R_full))
+    ids = rng.choice(R_full, size=n, replace=False)
+    centres = rng.integers(0, I, size=n)
+    factors = 10.0 * np.exp(rng.standard_normal(n))
+    return ids, centres, factors
+
+
+def _build(name, cfg, S, R_full, I, N, rays, step, spikes, device, c_dt=C_LIGHT * DT) -> Workload:
+    rays = np.asarray(rays, dtype=np.int64)
+    R = len(rays)
+    rho_np, T_np, r_edge_np = _profiles(cfg, R_full, I, rays, step)
+    dev = torch.device(device)
+    f64 = torch.float64
+    rho = torch.as_tensor(rho_np, dtype=f64, device=dev)
+    T = torch.as_tensor(T_np, dtype=f64, device=dev)
+    r_edge = torch.as_tensor(r_edge_np, dtype=f64, device=dev).expand(R, I + 1).contiguous()
+    e_edge = 2.0 * 150.0 ** (torch.arange(N + 1, dtype=f64, device=dev) / N)
+    eps = _group_energies(e_edge)                                     # [N]
+
+    kappa_a = 1e-6 * (rho / 1e14)[:, :, None] * (eps / 10.0)[None, None, :] ** 2   # [R][I][N]
+    sign, weight = _species_sign_weight(S)
+    ka, et, ks, pn = [], [], [], []
+    for q in range(S):
+        mu = sign[q] * 2.0 * T
+        x = (eps[None, None, :] - mu[:, :, None]) / T[:, :, None]
+        f = _fermi_dirac(x)
+        eta_q = weight[q] * kappa_a * torch.exp(-x)
+        ka.append(kappa_a)
+        et.append(eta_q)
+        ks.append(2.0 * kappa_a)
+        pn.append(0.9 * f)
+    kappa_a = torch.stack(ka).contiguous()
+    eta = torch.stack(et).contiguous()
+    kappa_s = torch.stack(ks).contiguous()
+    psi_n = torch.stack(pn).contiguous()
+
+    if spikes:
+        ids, centres, factors = _spikes(cfg, R_full, I)
+        pos = {int(r): j for j, r in enumerate(rays)}
+        for rid, c, fac in zip(ids, centres, factors):
+            if int(rid) not in pos:
+                continue
+            j = pos[int(rid)]
+            lo, hi = max(0, int(c) - SPIKE_HALF_WIDTH), min(I, int(c) + SPIKE_HALF_WIDTH + 1)
+            kappa_a[:, j, lo:hi, :] *= fac
+            eta[:, j, lo:hi, :] *= fac
+            kappa_s[:, j, lo:hi, :] *= fac
+
+    nes_amp = (1e-7 * rho / 1e14)[None].expand(S, R, I).contiguous()
+    le = torch.log(eps)
+    nes_g = torch.exp(-((le[:, None] - le[None, :]) ** 2) / (2.0 * 0.3 ** 2)).contiguous()
+    return Workload(name=name, S=S, R=R, I=I, N=N, c_dt=float(c_dt), r_edge=r_edge,
+                    e_edge=e_edge.contiguous(), temp=T.contiguous(), kappa_a=kappa_a, eta=eta,
+                    kappa_s=kappa_s, psi_n=psi_n, nes_amp=nes_amp, nes_g=nes_g)
+
+
+def make(cfg: int, *, rays: Optional[Sequence[int]] = None, zones: Optional[int] = None,
+         groups: Optional[int] = None, species: Optional[int] = None, step: int = 0,
+         device="cpu") -> Workload:
+    """Inputs of workload `cfg` (0..4).
+
+    `rays` selects a subset of the configuration's rays (per-ray random draws are
+    made for the full ray count, so a subset equals the same rays of the full
+    workload).  `zones`, `groups`, `species` shrink the shape for quick tests
+    while keeping the recipe.  `step` applies that many drift steps (multi-step case).
+    """
+    c = CONFIGS[cfg]
+    R_full = c["R"]
+    I = zones or c["I"]
+    N = groups or c["N"]
+    S = species or c["S"]
+    if rays is None:
+        rays = range(R_full)
+    spikes = cfg == 2
+    name = c["name"]
+    return _build(name, cfg, S, R_full, I, N, rays, step, spikes, device)
+
+
+def make_custom(*, S=1, R=2, I=16, N=8, seed_cfg=0, device="cpu", **kw) -> Workload:
+    """A small workload with the standard recipe at an arbitrary shape."""
+    w = _build(f"custom-{R}r-{I}z-{N}g-{S}s", seed_cfg, S, R, I, N, range(R), 0, False, device)
+    return dataclasses.replace(w, **kw)

@@ -1,0 +1,197 @@
+/*
+ * tm.h - C ABI of libtm, an MI355X (gfx950) implementation of the implicit,
+ * ray-by-ray multi-group flux-limited diffusion (MGFLD) neutrino-transport step
+ * of the CHIMERA paper (Bruenn et al., arXiv 1809.05608).
+ *
+ * The operation: for every independent (species, ray) "system" of I radial zones
+ * and N energy groups, advance the zeroth angular moment psi from time level n to
+ * n+1 by backward Euler (eq. a58 with the flux of eq. a59 and limiter eq. a20,
+ * lapse a = 1, Gamma = 1).  The residual per cell is
+ *
+ *   G_{i,k} = psi - psi^n + c dt [ (A_{i+1/2} H_{i+1/2} - A_{i-1/2} H_{i-1/2}) / V_i
+ *                                  - eta (1 - psi) + kappa_a psi - S_{i,k} ]
+ *
+ * with emission/absorption with Pauli blocking (the source of eq. a54), and the
+ * zeroth moment of inelastic NES-like scattering S (Phi_0 terms of eq. d8 in the
+ * zone-centred discretisation of eq. d40).  The Newton iteration of eq. a62aa
+ * solves the linearised system of eq. a62ae: block tridiagonal in radius with
+ * dense N x N diagonal blocks and diagonal off-diagonal blocks.
+ *
+ * Geometry and energy grid (stated with eq. a59 and eqs. a01/a01b): zone centre
+ * R_i = (R_{i-1/2} + R_{i+1/2})/2, V_i = (R_{i+1/2}^3 - R_{i-1/2}^3)/3,
+ * A_{i+1/2} = R_{i+1/2}^2 (4 pi dropped), group centre
+ * eps_k^2 = (e_{k+1/2}^2 + e_{k+1/2} e_{k-1/2} + e_{k-1/2}^2)/3,
+ * W_k = (e_{k+1/2}^3 - e_{k-1/2}^3)/3.  Transport mean free path
+ * 1/lambda = kappa_a + eta + kappa_s (eqs. d10, d8c); edge value
+ * lambda_{i+1/2} = sqrt(lambda_i lambda_{i+1}).
+ * Limited flux, m = max((psi_i + psi_{i+1})/2, psi_floor), D = R_{i+1} - R_i:
+ *   H_{i+1/2} = -lambda m (psi_{i+1} - psi_i) / (3 D m + lambda |psi_{i+1} - psi_i|).
+ * NES kernels (eq. d3 weighted symmetry, eq. d4 detailed balance), T = temp_i:
+ *   K^out_{kk'} = nes_amp_i (eps_k eps_k'/(10 MeV)^2) nes_g[k][k'] (W_k'/mean W) min(1, e^{-(eps_k'-eps_k)/T})
+ *   K^in_{kk'}  = same with min(1, e^{+(eps_k'-eps_k)/T})
+ *   S_{i,k} = (1 - psi_k) sum_k' K^in_{kk'} psi_k' - psi_k sum_k' K^out_{kk'} (1 - psi_k')
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers (HBM), caller-owned, float64 unless
+ *    stated.  The library never frees or keeps them after the call returns.
+ *  - Layouts (row-major, last index fastest):
+ *      cell  [S][R][I][N]   kappa_a, eta, kappa_s, psi, psi_n, residual, rhs, x, mu, seed, gradients
+ *      zone  [R][I]         temp
+ *      sysz  [S][R][I]      nes_amp, g_nes_amp
+ *      edge  [R][I+1]       r_edge (cm), edge 0 is the inner boundary
+ *      sys   [S][R]         every tm_stats array
+ *      e_edge [N+1] (MeV) and nes_g [N][N] are shared by all systems.
+ *  - One context is bound to one HIP stream given at creation; work is ordered on
+ *    that stream.  A context is not thread-safe.  tm_newton_step synchronises the
+ *    stream (it reads back a per-iteration count of unconverged systems); the other
+ *    entry points are asynchronous.
+ *  - Errors are returned, never thrown.  Invalid shapes or null required pointers
+ *    return TM_ERR_INVALID_ARG before any device work; HIP failures return
+ *    TM_ERR_HIP with the message available from tm_last_error.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_ERR_INVALID_ARG = 1,   /* bad shape, null pointer, unsupported option          */
+    TM_ERR_HIP = 2,           /* a HIP runtime call failed (see tm_last_error)         */
+    TM_ERR_SINGULAR = 3,      /* an exactly zero pivot in some block factorisation     */
+    TM_ERR_NOT_CONVERGED = 4, /* some system missed the Newton tolerance in max_iter   */
+    TM_ERR_NONFINITE = 5,     /* NaN or Inf in some system's residual or update        */
+    TM_ERR_WORKSPACE = 6      /* caller workspace too small, or allocation failed      */
+} tm_status;
+
+/* terms bitmask */
+#define TM_TERM_DIFFUSION 1u  /* radial flux-limited diffusion (eqs. a58, a59, a20)    */
+#define TM_TERM_EMABS     2u  /* emission/absorption with Pauli blocking (eq. a54)    */
+#define TM_TERM_NES       4u  /* inelastic NES-like scattering, Phi_0 (eqs. d8, d40)  */
+#define TM_TERMS_ALL      7u
+
+#define TM_BC_ZERO_FLUX   0   /* psi^(1) = 0 at the boundary (inner: the paper's centre condition) */
+#define TM_BC_FREE_STREAM 1   /* outer only: psi^(1) = psi^(0) of the last zone (limit eq. a22)     */
+
+#define TM_LIMITER_NONE   0   /* F = 1 (pure diffusion, eq. a21)                       */
+#define TM_LIMITER_INTRP  1   /* F = F_intrp of eq. a20                                */
+
+#define TM_PREC_FP64  0       /* everything in float64                                 */
+#define TM_PREC_MIXED 1       /* block factorisation and solve in float32; residual,
+                                 update and conservation sums in float64 (Newton acts as
+                                 iterative refinement)                                  */
+
+/* per-system flags (tm_stats.flags) */
+#define TM_FLAG_NOT_CONVERGED 1
+#define TM_FLAG_NONFINITE     2
+#define TM_FLAG_ZERO_PIVOT    4
+
+#define TM_MAX_GROUPS 32
+
+typedef struct {
+    int32_t  n_species;   /* S >= 1                                                    */
+    int32_t  n_rays;      /* R >= 1                                                    */
+    int32_t  n_zones;     /* I >= 1                                                    */
+    int32_t  n_groups;    /* N, 1 <= N <= TM_MAX_GROUPS                                */
+    double   c_dt;        /* c * dt in cm (> 0)                                        */
+    int32_t  inner_bc;    /* must be TM_BC_ZERO_FLUX                                   */
+    int32_t  outer_bc;    /* TM_BC_ZERO_FLUX or TM_BC_FREE_STREAM                      */
+    uint32_t terms;       /* TM_TERM_* bitmask                                         */
+    int32_t  limiter;     /* TM_LIMITER_*                                              */
+    double   psi_floor;   /* floor of the edge mean in the limiter (> 0), e.g. 1e-300  */
+    int32_t  precision;   /* TM_PREC_*                                                 */
+} tm_problem;
+
+typedef struct {
+    const double *r_edge;   /* edge [R][I+1], cm, strictly increasing per ray           */
+    const double *e_edge;   /* [N+1] MeV, strictly increasing, > 0                      */
+    const double *kappa_a;  /* cell, cm^-1, absorption inverse mean free path            */
+    const double *eta;      /* cell, cm^-1, emissivity j (emission per state per length)  */
+    const double *kappa_s;  /* cell, cm^-1, isoenergetic scattering (transport opacity)   */
+    const double *temp;     /* zone, MeV (> 0), used by the NES detailed balance          */
+    const double *nes_amp;  /* sysz, cm^-1; may be NULL when TM_TERM_NES is off          */
+    const double *nes_g;    /* [N][N] symmetric shape; may be NULL when TM_TERM_NES is off */
+} tm_inputs;
+
+typedef struct {            /* every array is per system [S][R], device memory        */
+    double  *res_inf;       /* max |G| at the returned psi                              */
+    double  *res0_inf;      /* max |G| at the initial guess                             */
+    double  *n_tot;         /* sum_i V_i sum_k W_k psi (number, constants dropped)      */
+    double  *e_tot;         /* sum_i V_i sum_k W_k eps_k psi (energy)                   */
+    double  *budget_n;      /* n_tot - n_tot^n + B_N - Q_N - NES_N = sum V W G (eq. a62) */
+    double  *lum_n;         /* c A_{I+1/2} sum_k W_k H_{I+1/2,k} (number luminosity)      */
+    int32_t *iters;         /* Newton updates applied                                   */
+    int32_t *flags;         /* TM_FLAG_* bits                                           */
+} tm_stats;
+
+typedef struct tm_ctx tm_ctx;
+
+/* Create a context for one problem shape, bound to `hip_stream` (a hipStream_t, or
+ * NULL for the default stream) on the current device.  Allocates nothing on the
+ * device until a call needs workspace.  *out receives the context.               */
+tm_status tm_create(const tm_problem *problem, void *hip_stream, tm_ctx **out);
+
+/* Free the context and any workspace it allocated itself.                         */
+tm_status tm_destroy(tm_ctx *ctx);
+
+/* Device bytes of workspace needed to factor `batch_systems` systems per launch
+ * (0 means all S*R systems at once).  Returns 0 for an invalid problem.           */
+size_t tm_workspace_bytes(const tm_problem *problem, int64_t batch_systems);
+
+/* Hand the context caller-owned device workspace (>= tm_workspace_bytes(p, b) for
+ * some batch b >= 1); the context then launches the factorisation in batches that
+ * fit.  Without it, the context allocates workspace for all systems on first use.
+ * Pass NULL/0 to go back to self-allocated workspace.                              */
+tm_status tm_set_workspace(tm_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Residual G(psi) (eq. a58 times c dt) into `residual` (cell).  If `blocks` is not
+ * NULL it receives the exact Jacobian in block form, [S][R][I][N][N+2]: row k of
+ * zone i holds the dense block A_i[k][0..N-1], then bm_{i,k}, bp_{i,k} (eq. a62ae).
+ * This debug output is the only path on which a Jacobian reaches HBM.             */
+tm_status tm_assemble(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
+                      const double *psi, double *residual, double *blocks);
+
+/* Solve J(psi) x = rhs (transpose = 0) or J(psi)^T x = rhs (transpose != 0) for
+ * every system by block-Thomas elimination (eq. a62ae) with partial pivoting inside
+ * each dense block.  rhs and x are cell arrays and may alias.  In TM_PREC_MIXED the
+ * factorisation and solve run in float32 (x is the float32 solution widened).      */
+tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
+                          const double *rhs, double *x, int32_t transpose);
+
+/* Backward-Euler Newton iteration (eq. a62aa) for psi^{n+1} of every system.
+ * psi holds the initial guess on entry (usually a copy of psi_n) and psi^{n+1} on
+ * return.  Per system, an update J delta = -G is applied while
+ * max|G(psi)| > rtol * max|G(psi_initial)| and fewer than max_iter updates have
+ * been made (rtol = 0 runs exactly max_iter updates).  `stats` (all pointers
+ * device, may be NULL as a whole) receives the per-system results at the returned
+ * psi.  Returns TM_OK, or the worst of TM_ERR_NONFINITE, TM_ERR_SINGULAR,
+ * TM_ERR_NOT_CONVERGED over systems (per-system detail in stats.flags).           */
+tm_status tm_newton_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
+                         double *psi, int32_t max_iter, double rtol, tm_stats *stats);
+
+/* Adjoint of the converged step.  Solves J(psi_np1)^T mu = seed (seed = dJ/dpsi^{n+1})
+ * and returns the vector-Jacobian products of the objective through the solution:
+ *   g_theta = -mu^T dG/dtheta  for theta in {kappa_a, eta, kappa_s, nes_amp},
+ *   mu itself is dJ/dpsi^n (dG/dpsi^n = -1).
+ * Every gradient pointer may be NULL to skip it; mu must not be NULL.  Always FP64. */
+tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
+                          const double *psi_np1, const double *seed, double *mu,
+                          double *g_kappa_a, double *g_eta, double *g_kappa_s,
+                          double *g_nes_amp);
+
+/* Human-readable name of a status code (static storage).                          */
+const char *tm_status_string(tm_status status);
+
+/* Last error message recorded on the context (empty string when none).            */
+const char *tm_last_error(const tm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

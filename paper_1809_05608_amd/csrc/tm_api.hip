@@ -1,0 +1,388 @@
+// Host side of the libtm C ABI (include/tm.h): argument validation, workspace,
+// launch sequencing of the Newton iteration and the adjoint, status reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tm.h"
+#include "tm_kernels.hpp"
+
+struct tm_ctx {
+    tm_problem p;
+    hipStream_t stream;
+    int device;
+    std::string err;
+    // workspace (factors), either caller-owned or allocated here
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    // small internal device buffers
+    tmk::Consts* consts = nullptr;
+    double* res = nullptr;      // [nsys]
+    double* res0 = nullptr;     // [nsys]
+    int* active = nullptr;      // [nsys]
+    int* iters = nullptr;       // [nsys]
+    int* flags = nullptr;       // [nsys]
+    int* count = nullptr;       // [1]
+    double* gbuf = nullptr;     // [cells] residual for the Newton right-hand side
+    int* h_count = nullptr;     // pinned host
+};
+
+namespace {
+
+long long n_systems(const tm_problem& p) { return (long long)p.n_species * p.n_rays; }
+long long n_cells(const tm_problem& p) { return n_systems(p) * p.n_zones * p.n_groups; }
+
+bool valid_problem(const tm_problem* p, std::string* why) {
+    auto fail = [&](const char* m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!p) return fail("problem is NULL");
+    if (p->n_species < 1 || p->n_rays < 1 || p->n_zones < 1) return fail("S, R and I must be >= 1");
+    if (p->n_groups < 1 || p->n_groups > TM_MAX_GROUPS) return fail("N must be in [1, 32]");
+    if (!(p->c_dt > 0.0) || !std::isfinite(p->c_dt)) return fail("c_dt must be finite and > 0");
+    if (p->inner_bc != TM_BC_ZERO_FLUX) return fail("inner_bc must be TM_BC_ZERO_FLUX");
+    if (p->outer_bc != TM_BC_ZERO_FLUX && p->outer_bc != TM_BC_FREE_STREAM) return fail("bad outer_bc");
+    if (p->terms & ~TM_TERMS_ALL) return fail("unknown bit in terms");
+    if (p->limiter != TM_LIMITER_NONE && p->limiter != TM_LIMITER_INTRP) return fail("bad limiter");
+    if (!(p->psi_floor > 0.0)) return fail("psi_floor must be > 0");
+    if (p->precision != TM_PREC_FP64 && p->precision != TM_PREC_MIXED) return fail("bad precision");
+    if (n_systems(*p) > 0x7fffffffLL) return fail("too many systems");
+    return true;
+}
+
+tmk::Shape shape_of(const tm_problem& p) {
+    tmk::Shape s;
+    s.S = p.n_species;
+    s.R = p.n_rays;
+    s.I = p.n_zones;
+    s.N = p.n_groups;
+    s.c_dt = p.c_dt;
+    s.outer_bc = p.outer_bc;
+    s.terms = p.terms;
+    s.limiter = p.limiter;
+    s.psi_floor = p.psi_floor;
+    return s;
+}
+
+tmk::Fields fields_of(const tm_inputs& in) {
+    tmk::Fields f;
+    f.r_edge = in.r_edge;
+    f.kappa_a = in.kappa_a;
+    f.eta = in.eta;
+    f.kappa_s = in.kappa_s;
+    f.temp = in.temp;
+    f.nes_amp = in.nes_amp;
+    return f;
+}
+
+tm_status set_err(tm_ctx* c, tm_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+tm_status hip_check(tm_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return TM_OK;
+    return set_err(c, TM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TM_TRY(expr)                        \
+    do {                                    \
+        tm_status _s = (expr);              \
+        if (_s != TM_OK) return _s;         \
+    } while (0)
+
+tm_status check_inputs(tm_ctx* c, const tm_inputs* in, bool need_opacity = true) {
+    if (!in) return set_err(c, TM_ERR_INVALID_ARG, "inputs is NULL");
+    if (!in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
+    if (need_opacity && (!in->kappa_a || !in->eta || !in->kappa_s))
+        return set_err(c, TM_ERR_INVALID_ARG, "kappa_a, eta and kappa_s are required");
+    if ((c->p.terms & TM_TERM_NES) && (!in->nes_amp || !in->nes_g || !in->temp))
+        return set_err(c, TM_ERR_INVALID_ARG, "nes_amp, nes_g and temp are required when TM_TERM_NES is on");
+    return TM_OK;
+}
+
+// Internal per-context buffers that do not depend on the factor workspace.
+tm_status ensure_small(tm_ctx* c) {
+    if (c->consts) return TM_OK;
+    const long long ns = n_systems(c->p);
+    TM_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->consts, sizeof(tmk::Consts)), "hipMalloc consts"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->res, ns * sizeof(double)), "hipMalloc res"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->res0, ns * sizeof(double)), "hipMalloc res0"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->active, ns * sizeof(int)), "hipMalloc active"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->iters, ns * sizeof(int)), "hipMalloc iters"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->flags, ns * sizeof(int)), "hipMalloc flags"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->count, sizeof(int)), "hipMalloc count"));
+    TM_TRY(hip_check(c, hipHostMalloc((void**)&c->h_count, sizeof(int)), "hipHostMalloc"));
+    return TM_OK;
+}
+
+tm_status ensure_gbuf(tm_ctx* c) {
+    if (c->gbuf) return TM_OK;
+    return hip_check(c, hipMalloc((void**)&c->gbuf, n_cells(c->p) * sizeof(double)), "hipMalloc residual buffer");
+}
+
+// Systems per factor launch that fit the workspace; allocates all-systems workspace if none.
+tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
+    const size_t per = tmk::factor_ws_bytes_per_system(c->p.n_zones, c->p.n_groups, fp32);
+    const long long ns = n_systems(c->p);
+    if (!c->ws) {
+        // self-allocate: all systems if they fit in 70% of free memory, else the largest power-of-two share
+        size_t freeb = 0, totalb = 0;
+        TM_TRY(hip_check(c, hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo"));
+        long long b = ns;
+        while (b > 1 && (double)b * per > 0.7 * (double)freeb) b = (b + 1) / 2;
+        const size_t bytes = (size_t)b * per;
+        hipError_t e = hipMalloc(&c->ws, bytes);
+        if (e != hipSuccess) {
+            c->ws = nullptr;
+            return set_err(c, TM_ERR_WORKSPACE, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        c->ws_bytes = bytes;
+        c->ws_owned = true;
+    }
+    long long b = (long long)(c->ws_bytes / per);
+    if (b < 1) return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
+    *batch = std::min(b, ns);
+    return TM_OK;
+}
+
+tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double rhs_sign,
+                     double* x, double* psi_out, const int* active, bool fp32, bool transpose) {
+    long long batch = 0;
+    TM_TRY(factor_batch(c, fp32, &batch));
+    const int NT = tmk::padded_groups(c->p.n_groups);
+    const size_t es = fp32 ? 4 : 8;
+    tmk::FactorArgs a;
+    a.sh = shape_of(c->p);
+    a.f = fields_of(*in);
+    a.cs = c->consts;
+    a.psi = psi;
+    a.rhs = rhs;
+    a.rhs_sign = rhs_sign;
+    a.x = x;
+    a.psi_out = psi_out;
+    a.active = active;
+    a.flags = c->flags;
+    a.iters = psi_out ? c->iters : nullptr;
+    a.wsC = c->ws;
+    a.wsY = (char*)c->ws + (size_t)batch * c->p.n_zones * NT * NT * es;
+    const long long ns = n_systems(c->p);
+    for (long long s0 = 0; s0 < ns; s0 += batch) {
+        a.sys0 = s0;
+        a.nsys = std::min(batch, ns - s0);
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, c->stream), "factor kernel"));
+    }
+    return TM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tm_status_string(tm_status s) {
+    switch (s) {
+        case TM_OK: return "TM_OK";
+        case TM_ERR_INVALID_ARG: return "TM_ERR_INVALID_ARG";
+        case TM_ERR_HIP: return "TM_ERR_HIP";
+        case TM_ERR_SINGULAR: return "TM_ERR_SINGULAR";
+        case TM_ERR_NOT_CONVERGED: return "TM_ERR_NOT_CONVERGED";
+        case TM_ERR_NONFINITE: return "TM_ERR_NONFINITE";
+        case TM_ERR_WORKSPACE: return "TM_ERR_WORKSPACE";
+    }
+    return "TM_UNKNOWN_STATUS";
+}
+
+const char* tm_last_error(const tm_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+size_t tm_workspace_bytes(const tm_problem* p, int64_t batch_systems) {
+    if (!valid_problem(p, nullptr) || batch_systems < 0) return 0;
+    const long long ns = n_systems(*p);
+    const long long b = batch_systems == 0 ? ns : std::min<long long>(batch_systems, ns);
+    return (size_t)b * tmk::factor_ws_bytes_per_system(p->n_zones, p->n_groups, p->precision == TM_PREC_MIXED);
+}
+
+tm_status tm_create(const tm_problem* p, void* stream, tm_ctx** out) {
+    if (!out) return TM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::string why;
+    if (!valid_problem(p, &why)) return TM_ERR_INVALID_ARG;
+    tm_ctx* c = new tm_ctx();
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return TM_ERR_HIP;
+    }
+    *out = c;
+    return TM_OK;
+}
+
+tm_status tm_destroy(tm_ctx* c) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if (c->consts) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->consts);
+        (void)hipFree(c->res);
+        (void)hipFree(c->res0);
+        (void)hipFree(c->active);
+        (void)hipFree(c->iters);
+        (void)hipFree(c->flags);
+        (void)hipFree(c->count);
+        (void)hipHostFree(c->h_count);
+    }
+    if (c->gbuf) (void)hipFree(c->gbuf);
+    if (c->ws && c->ws_owned) (void)hipFree(c->ws);
+    delete c;
+    return TM_OK;
+}
+
+tm_status tm_set_workspace(tm_ctx* c, void* dev, size_t bytes) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if ((dev == nullptr) != (bytes == 0))
+        return set_err(c, TM_ERR_INVALID_ARG, "workspace pointer and size must both be set or both be 0");
+    if (dev && bytes < tmk::factor_ws_bytes_per_system(c->p.n_zones, c->p.n_groups, c->p.precision == TM_PREC_MIXED))
+        return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
+    if (c->ws && c->ws_owned) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->ws);
+    }
+    c->ws = dev;
+    c->ws_bytes = bytes;
+    c->ws_owned = false;
+    return TM_OK;
+}
+
+tm_status tm_assemble(tm_ctx* c, const tm_inputs* in, const double* psi_n, const double* psi, double* residual,
+                      double* blocks) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    if (!psi_n || !psi || !residual) return set_err(c, TM_ERR_INVALID_ARG, "psi_n, psi and residual are required");
+    TM_TRY(ensure_small(c));
+    const tmk::Shape sh = shape_of(c->p);
+    const tmk::Fields f = fields_of(*in);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    tmk::ResidualOut o{};
+    o.res = c->res;
+    TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, residual, 1.0, o, c->stream),
+                     "residual kernel"));
+    if (blocks)
+        TM_TRY(hip_check(c, tmk::launch_blocks(sh, f, c->consts, psi, blocks, c->stream), "blocks kernel"));
+    return TM_OK;
+}
+
+tm_status tm_factor_solve(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double* x,
+                          int32_t transpose) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    if (!psi || !rhs || !x) return set_err(c, TM_ERR_INVALID_ARG, "psi, rhs and x are required");
+    TM_TRY(ensure_small(c));
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, c->p.n_groups, c->consts, c->stream),
+                     "setup kernel"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->flags, 0, n_systems(c->p) * sizeof(int), c->stream), "memset flags"));
+    return run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, c->p.precision == TM_PREC_MIXED, transpose != 0);
+}
+
+tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, double* psi, int32_t max_iter,
+                         double rtol, tm_stats* stats) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    if (!psi_n || !psi) return set_err(c, TM_ERR_INVALID_ARG, "psi_n and psi are required");
+    if (max_iter < 0 || !(rtol >= 0.0)) return set_err(c, TM_ERR_INVALID_ARG, "max_iter >= 0 and rtol >= 0 required");
+    TM_TRY(ensure_small(c));
+    TM_TRY(ensure_gbuf(c));
+    const long long ns = n_systems(c->p);
+    const tmk::Shape sh = shape_of(c->p);
+    const tmk::Fields f = fields_of(*in);
+    const bool fp32 = c->p.precision == TM_PREC_MIXED;
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->iters, 0, ns * sizeof(int), c->stream), "memset iters"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->flags, 0, ns * sizeof(int), c->stream), "memset flags"));
+
+    for (int it = 0; it <= max_iter; ++it) {
+        tmk::ResidualOut o{};
+        o.res = c->res;
+        o.res0 = c->res0;
+        o.set_res0 = it == 0;
+        o.active = c->active;
+        o.iters = c->iters;
+        o.max_iter = max_iter;
+        o.rtol = rtol;
+        TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, c->gbuf, 1.0, o, c->stream),
+                         "residual kernel"));
+        if (it == max_iter) break;
+        TM_TRY(hip_check(c, tmk::launch_count_active(c->active, ns, c->count, c->stream), "count kernel"));
+        TM_TRY(hip_check(c, hipMemcpyAsync(c->h_count, c->count, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                         "copy count"));
+        TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+        if (*c->h_count == 0) break;
+        TM_TRY(run_factor(c, in, psi, c->gbuf, -1.0, nullptr, psi, c->active, fp32, false));
+    }
+
+    // final statistics at the returned psi
+    tmk::ResidualOut o{};
+    o.res = c->res;
+    o.res0 = c->res0;
+    o.set_res0 = 0;
+    o.flags = c->flags;
+    o.rtol = rtol;
+    o.max_iter = max_iter;
+    o.stats = stats != nullptr;
+    if (stats) {
+        o.n_tot = stats->n_tot;
+        o.e_tot = stats->e_tot;
+        o.budget = stats->budget_n;
+        o.lum = stats->lum_n;
+    }
+    TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, nullptr, 1.0, o, c->stream),
+                     "residual kernel"));
+    if (stats) {
+        auto cp = [&](void* dst, const void* src, size_t bytes) -> tm_status {
+            if (!dst) return TM_OK;
+            return hip_check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "copy stats");
+        };
+        TM_TRY(cp(stats->res_inf, c->res, ns * sizeof(double)));
+        TM_TRY(cp(stats->res0_inf, c->res0, ns * sizeof(double)));
+        TM_TRY(cp(stats->iters, c->iters, ns * sizeof(int)));
+        TM_TRY(cp(stats->flags, c->flags, ns * sizeof(int)));
+    }
+    // worst status over systems
+    std::vector<int> fl(ns);
+    TM_TRY(hip_check(c, hipMemcpyAsync(fl.data(), c->flags, ns * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                     "copy flags"));
+    TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+    int any = 0;
+    for (int v : fl) any |= v;
+    if (any & TM_FLAG_NONFINITE) return set_err(c, TM_ERR_NONFINITE, "non-finite residual in some system");
+    if (any & TM_FLAG_ZERO_PIVOT) return set_err(c, TM_ERR_SINGULAR, "zero pivot in some block");
+    if (any & TM_FLAG_NOT_CONVERGED) return set_err(c, TM_ERR_NOT_CONVERGED, "some system missed rtol");
+    c->err.clear();
+    return TM_OK;
+}
+
+tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, const double* psi_np1,
+                          const double* seed, double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    if (!psi_np1 || !seed || !mu) return set_err(c, TM_ERR_INVALID_ARG, "psi_np1, seed and mu are required");
+    (void)psi_n;
+    TM_TRY(ensure_small(c));
+    const tmk::Shape sh = shape_of(c->p);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->flags, 0, n_systems(c->p) * sizeof(int), c->stream), "memset flags"));
+    TM_TRY(run_factor(c, in, psi_np1, seed, 1.0, mu, nullptr, nullptr, /*fp32=*/false, /*transpose=*/true));
+    if (g_ka || g_eta || g_ks || g_amp)
+        TM_TRY(hip_check(c, tmk::launch_vjp(sh, fields_of(*in), c->consts, psi_np1, mu, g_ka, g_eta, g_ks, g_amp,
+                                            c->stream),
+                         "vjp kernel"));
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,375 @@
+// Fused Jacobian assembly + block-Thomas factor/solve of the linearised transport
+// step (eq. a62ae), one (species, ray) system per SL-lane group of a wavefront.
+//
+// Layout on the chip: lane k of a group owns row k of the current zone's dense N x N
+// block (N <= NT <= 32, SL = 16 or 32 lanes per system, 4 or 2 systems per wave64).
+// The sweep over radial zones is sequential inside the group; systems run in parallel.
+// Per zone the row is assembled in registers (flux-limited diffusion derivatives,
+// emission/absorption, dense NES coupling), the Schur complement
+//   Ahat_i = A_i - diag(bm_i) C_{i-1}
+// is formed with the previous factor row still in registers, and an unnormalised
+// in-place Gauss-Jordan elimination with partial pivoting produces
+//   C_i = Ahat_i^{-1} diag(bp_i)  and  y_i = Ahat_i^{-1} (r_i - bm_i * y_{i-1}).
+// Pivot search is a packed-key max over the group (DPP row reductions plus a
+// 16-lane swap); the pivot row is broadcast through LDS; row ownership is left
+// permuted during the elimination and restored once per zone through LDS.
+// C_i and y_i are the only quantities that reach HBM (workspace, [zone][m][k]
+// so that both sweeps are coalesced); the backward sweep forms
+//   x_i = y_i - C_i x_{i+1}
+// and either writes x or adds it to psi (Newton update, eq. a62aa).
+// The transposed variant (adjoint) assembles the same rows, transposes the block
+// through LDS and swaps the roles of bm and bp.
+#include "tm_kernels.hpp"
+
+namespace tmk {
+
+__device__ __forceinline__ uint32_t abs_key_bits(double v) {
+    return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+}
+__device__ __forceinline__ uint32_t abs_key_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
+
+__device__ __forceinline__ double texp(double x) { return exp(x); }
+__device__ __forceinline__ float texp(float x) { return __expf(x); }
+
+// Max of a 32-bit key over each SL-lane group (SL = 16 or 32) of the wavefront.
+template <int SL>
+__device__ __forceinline__ uint32_t group_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    if constexpr (SL == 32) {
+        auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);                   // rows 0<->1, 2<->3
+        v = max((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    return v;
+}
+
+// Intra-wavefront ordering point for LDS exchange between lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int NT>
+struct alignas(16) SysLds {
+    static constexpr int FS = NT + 16 / (int)sizeof(T);   // row stride: >= NT + 2, multiple of 16 bytes
+    T prow[FS];        // pivot row: [0, NT) entries, NT right-hand side, NT+1 diagonal of B
+    T bc[FS];          // broadcast of a zone's psi row (NES) or of x_{i+1} (back substitution)
+    T dd[FS];          // NES neighbour factors exp(-(eps_{j+1} - eps_j)/T)
+    T fix[NT][FS];     // row-ownership fix-up and transpose staging
+};
+
+template <typename T, int NT, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
+    constexpr int SL = NT > 16 ? 32 : 16;
+    constexpr int SPW = 64 / SL;
+    constexpr int SPB = (kBlock / 64) * SPW;
+    __shared__ SysLds<T, NT> lds_all[SPB];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / SL, k = lane % SL;
+    const long long sb = (long long)blockIdx.x * SPB + wave * SPW + sub;    // system within the batch
+    const bool in_batch = sb < A.nsys;
+    const long long sbc = in_batch ? sb : A.nsys - 1;                        // clamped for loads
+    const long long sys = A.sys0 + sbc;                                      // global system index
+    const bool live = in_batch && (A.active == nullptr || A.active[sys] != 0);
+    if (__ballot(live) == 0) return;                                         // whole wave idle
+
+    SysLds<T, NT>& L = lds_all[wave * SPW + sub];
+    const Shape& sh = A.sh;
+    const int N = sh.N, I = sh.I;
+    const bool is_row = k < NT;      // owns a (possibly padded) row of the block
+    const bool real = k < N;         // owns a real energy-group row
+    const int kk = real ? k : 0;     // safe group index for loads
+    const int kr = is_row ? k : 0;   // safe row index for LDS
+    const int ray = (int)(sys % sh.R);
+    const double* re = A.f.r_edge + (size_t)ray * (I + 1);
+    const size_t cell0 = (size_t)sys * I * N;
+    const double* psi = A.psi + cell0;
+    const double* ka = A.f.kappa_a + cell0;
+    const double* et = A.f.eta + cell0;
+    const double* ks = A.f.kappa_s + cell0;
+    const double* rhs = A.rhs + cell0;
+    const double* tz = A.f.temp + (size_t)ray * I;
+    const double* az = (sh.terms & kNes) ? A.f.nes_amp + (size_t)sys * I : nullptr;
+    const double c = sh.c_dt;
+    const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+    T* wsC = reinterpret_cast<T*>(A.wsC) + (size_t)sbc * I * NT * NT;
+    T* wsY = reinterpret_cast<T*>(A.wsY) + (size_t)sbc * I * NT;
+    const bool store = live && real;
+
+    // row k of the NES kernel shape (zone independent)
+    T Prow[NT];
+#pragma unroll
+    for (int kp = 0; kp < NT; ++kp) Prow[kp] = (T)A.cs->P[k < kMaxN ? k : 0][kp];
+    const double de_k = A.cs->de[k < kMaxN ? k : 0];
+
+    // ---------------------------------------------------------------- forward sweep
+    T a[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) a[j] = (T)0;
+    T ycar = (T)0;
+    double psi_c = real ? psi[kk] : 0.0;
+    double sig_c = real ? ka[kk] + et[kk] : 0.0;
+    double lam_c = real ? 1.0 / (sig_c + ks[kk]) : 1.0;
+    double dHu_lo = 0.0, dHv_lo = 0.0, bp_prev = 0.0;
+    bool zp = false;
+
+    for (int i = 0; i < I; ++i) {
+        // next zone, own group
+        double psi_n1 = 0.0, sig_n1 = 0.0, lam_n1 = 1.0;
+        if (i + 1 < I && real) {
+            const size_t cn = (size_t)(i + 1) * N + kk;
+            psi_n1 = psi[cn];
+            sig_n1 = ka[cn] + et[cn];
+            lam_n1 = 1.0 / (sig_n1 + ks[cn]);
+        }
+        const double rlo = re[i], rhi = re[i + 1];
+        const double V = shell_volume(rlo, rhi);
+        const double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double dHu_hi = 0.0, dHv_hi = 0.0, V_hi = 1.0;
+        if (i + 1 < I) {
+            const double rp = re[i + 2];
+            const double D_hi = 0.5 * (rhi + rp) - 0.5 * (rlo + rhi);
+            V_hi = shell_volume(rhi, rp);
+            if (diff && real) {
+                const EdgeFlux e = edge_flux(psi_c, psi_n1, sqrt(lam_c * lam_n1), D_hi, sh.psi_floor, sh.limiter);
+                dHu_hi = e.dHu;
+                dHv_hi = e.dHv;
+            }
+        } else if (sh.outer_bc == 1) {
+            dHu_hi = 1.0;                                   // free streaming: H = psi of the last zone
+        }
+        double diag = 1.0, bm = 0.0, bp = 0.0, bm_next = 0.0;
+        if (diff) {
+            diag += c * (A_hi * dHu_hi - A_lo * dHv_lo) / V;
+            if (i + 1 < I) bp = c * A_hi * dHv_hi / V;
+            if (i > 0) bm = -c * A_lo * dHu_lo / V;
+            if (i + 1 < I) bm_next = -c * A_hi * dHu_hi / V_hi;
+        }
+        if (emabs) diag += c * sig_c;
+
+        // ---- row k of the dense block A_i (before the Schur update)
+        T row[NT];
+#pragma unroll
+        for (int kp = 0; kp < NT; ++kp) row[kp] = (T)0;
+        if (nes) {
+            const double amp = az[i];
+            const double Tz = tz[i];
+            if (is_row) {
+                L.bc[k] = real ? (T)psi_c : (T)0;
+                L.dd[k] = (k + 1 < N) ? texp((T)(-de_k / Tz)) : (T)0;
+            }
+            wave_sync();
+            const T pk = (T)psi_c;
+            // out factor: exp(-(eps_k' - eps_k)/T) for k' > k, 1 otherwise (ascending product)
+            T er = (T)1, so = (T)0, si = (T)0;
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) {
+                if (kp > 0) er = (kp > k) ? er * L.dd[kp - 1] : (T)1;
+                const T po = Prow[kp] * er;
+                so = fma(po, (T)1 - L.bc[kp], so);
+                row[kp] = pk * po;                        // psi_k K^out_{kk'} / amp
+            }
+            // in factor: exp(-(eps_k - eps_k')/T) for k' < k, 1 otherwise (descending product)
+            T el = (T)1;
+#pragma unroll
+            for (int kp = NT - 1; kp >= 0; --kp) {
+                el = (kp < k) ? el * L.dd[kp] : (T)1;
+                const T pi = Prow[kp] * el;
+                si = fma(pi, L.bc[kp], si);
+                row[kp] = fma((T)1 - pk, pi, row[kp]);   // + (1 - psi_k) K^in_{kk'} / amp
+            }
+            const T ca = (T)(-c * amp);
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) row[kp] = (kp < N) ? ca * row[kp] : (T)0;
+            diag += c * amp * (double)(si + so);
+        }
+        if (real) {
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) row[kp] += (kp == k) ? (T)diag : (T)0;
+        } else {
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) row[kp] = (kp == k) ? (T)1 : (T)0;   // padded identity row
+            bm = bp = bm_next = 0.0;
+        }
+
+        // ---- Schur complement and right-hand side
+        T g = real ? (T)(A.rhs_sign * rhs[(size_t)i * N + kk]) : (T)0;
+        T bcoef;
+        if constexpr (!TRANS) {
+            const T s = (T)bm;
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) a[kp] = fma(-s, a[kp], row[kp]);
+            g = fma(-s, ycar, g);
+            bcoef = (T)bp;
+        } else {
+            if (is_row) {
+#pragma unroll
+                for (int kp = 0; kp < NT; ++kp) L.fix[k][kp] = row[kp];
+            }
+            wave_sync();
+            const T s = real ? (T)bp_prev : (T)0;
+#pragma unroll
+            for (int m = 0; m < NT; ++m) a[m] = fma(-s, a[m], is_row ? L.fix[m][kr] : (T)0);
+            wave_sync();
+            g = fma(-s, ycar, g);
+            bcoef = (T)bm_next;
+        }
+
+        // ---- in-place Gauss-Jordan with partial pivoting on [Ahat | diag(b) | g]
+        bool used = !is_row;
+        T mypiv = (T)1;
+        int mycol = 0;
+        int pstep[NT];
+#pragma unroll
+        for (int cc = 0; cc < NT; ++cc) {
+            const T ac = a[cc];
+            const uint32_t key =
+                used ? 0u : ((abs_key_bits(ac) & ~(uint32_t)(SL - 1)) | (uint32_t)(SL - 1 - k));
+            const uint32_t kmax = group_max<SL>(key);
+            const int p = SL - 1 - (int)(kmax & (SL - 1));
+            const bool isp = (k == p);
+            if (isp) {
+#pragma unroll
+                for (int j = 0; j < NT; ++j) L.prow[j] = a[j];
+                L.prow[NT] = g;
+                L.prow[NT + 1] = bcoef;
+            }
+            wave_sync();
+            const T piv = L.prow[cc];
+            zp |= (piv == (T)0);
+            const T pinv = (T)1 / piv;
+            const T f = isp ? (T)0 : ac * pinv;
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                if (j != cc) a[j] = fma(-f, L.prow[j], a[j]);
+            g = fma(-f, L.prow[NT], g);
+            const T bpiv = L.prow[NT + 1];
+            a[cc] = isp ? bpiv : -f * bpiv;
+            if (isp) {
+                used = true;
+                mypiv = piv;
+                mycol = cc;
+            }
+            pstep[cc] = p;
+            wave_sync();
+        }
+
+        // ---- restore row ownership: lane holding unknown mycol writes its scaled row
+        if (is_row) {
+            const T ip = (T)1 / mypiv;
+#pragma unroll
+            for (int cc = 0; cc < NT; ++cc) L.fix[mycol][pstep[cc]] = a[cc] * ip;
+            L.fix[mycol][NT] = g * ip;
+        }
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < NT; ++m) a[m] = is_row ? L.fix[kr][m] : (T)0;
+        ycar = is_row ? L.fix[kr][NT] : (T)0;
+        wave_sync();
+
+        if (store) {
+            T* Cz = wsC + (size_t)i * NT * NT;
+#pragma unroll
+            for (int m = 0; m < NT; ++m)
+                if (m < N) Cz[m * NT + k] = a[m];
+            wsY[(size_t)i * NT + k] = ycar;
+        }
+
+        psi_c = psi_n1;
+        sig_c = sig_n1;
+        lam_c = lam_n1;
+        dHu_lo = dHu_hi;
+        dHv_lo = dHv_hi;
+        bp_prev = bp;
+    }
+
+    // zero-pivot report (any lane of the system)
+    const uint32_t zany = group_max<SL>(zp ? 1u : 0u);
+    if (live && k == 0 && zany && A.flags) A.flags[sys] |= 4;
+
+    // ---------------------------------------------------------------- backward sweep
+    double* outp = A.psi_out ? A.psi_out + cell0 : nullptr;
+    double* xp = A.x ? A.x + cell0 : nullptr;
+    T cr[NT], crn[NT];
+    T yv = (T)0, yn = (T)0;
+    {
+        const T* Cz = wsC + (size_t)(I - 1) * NT * NT;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? Cz[m * NT + k] : (T)0;
+        yv = real ? wsY[(size_t)(I - 1) * NT + k] : (T)0;
+    }
+    T dnext = (T)0;
+    for (int i = I - 1; i >= 0; --i) {
+        if (i > 0) {
+            const T* Cz = wsC + (size_t)(i - 1) * NT * NT;
+#pragma unroll
+            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? Cz[m * NT + k] : (T)0;
+            yn = real ? wsY[(size_t)(i - 1) * NT + k] : (T)0;
+        }
+        T dl = yv;
+        if (i + 1 < I) {
+            if (is_row) L.bc[k] = dnext;
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < NT; ++m) dl = fma(-cr[m], L.bc[m], dl);
+            wave_sync();
+        }
+        if (store) {
+            const size_t ci = (size_t)i * N + k;
+            if (outp) outp[ci] += (double)dl;
+            else xp[ci] = (double)dl;
+        }
+        dnext = dl;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) cr[m] = crn[m];
+        yv = yn;
+    }
+    if (live && k == 0 && A.iters && A.psi_out) A.iters[sys] += 1;
+}
+
+size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
+    const int NT = padded_groups(N);
+    if (NT < 0) return 0;
+    const size_t es = fp32 ? 4 : 8;
+    return (size_t)I * NT * (NT + 1) * es;
+}
+
+template <typename T, int NT, bool TR>
+static void launch_t(const FactorArgs& a, hipStream_t st) {
+    constexpr int SL = NT > 16 ? 32 : 16;
+    constexpr int SPB = (kBlock / 64) * (64 / SL);
+    const long long blocks = (a.nsys + SPB - 1) / SPB;
+    hipLaunchKernelGGL((k_factor<T, NT, TR>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+}
+
+template <int NT>
+static void launch_nt(const FactorArgs& a, bool fp32, bool tr, hipStream_t st) {
+    if (fp32) {
+        if (tr) launch_t<float, NT, true>(a, st);
+        else launch_t<float, NT, false>(a, st);
+    } else {
+        if (tr) launch_t<double, NT, true>(a, st);
+        else launch_t<double, NT, false>(a, st);
+    }
+}
+
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, hipStream_t st) {
+    switch (padded_groups(a.sh.N)) {
+        case 4: launch_nt<4>(a, fp32, transpose, st); break;
+        case 8: launch_nt<8>(a, fp32, transpose, st); break;
+        case 12: launch_nt<12>(a, fp32, transpose, st); break;
+        case 16: launch_nt<16>(a, fp32, transpose, st); break;
+        case 20: launch_nt<20>(a, fp32, transpose, st); break;
+        case 24: launch_nt<24>(a, fp32, transpose, st); break;
+        case 28: launch_nt<28>(a, fp32, transpose, st); break;
+        case 32: launch_nt<32>(a, fp32, transpose, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tmk

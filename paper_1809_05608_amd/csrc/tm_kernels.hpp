@@ -1,0 +1,63 @@
+// Kernel launch interfaces of libtm (internal; the public C ABI is include/tm.h).
+#pragma once
+
+#include "tm_device.hpp"
+
+namespace tmk {
+
+// Outputs of the residual / statistics kernel, all per system of the launch.
+struct ResidualOut {
+    double* res;        // max |G|                       (required)
+    double* res0;       // written when set_res0 != 0     (nullable)
+    int* active;        // Newton activity flag           (nullable)
+    const int* iters;   // updates applied so far         (nullable)
+    int* flags;         // TM_FLAG_* bits                 (nullable)
+    double* n_tot;      // statistics, written when stats != 0 (nullable)
+    double* e_tot;
+    double* budget;
+    double* lum;
+    int set_res0;
+    int stats;
+    int max_iter;
+    double rtol;
+};
+
+struct FactorArgs {
+    Shape sh;
+    Fields f;
+    const Consts* cs;
+    const double* psi;        // state at which J is evaluated [S][R][I][N]
+    const double* rhs;        // right-hand side, cell array, multiplied by rhs_sign
+    double rhs_sign;
+    double* x;                // solution output (nullable when psi_out is set)
+    double* psi_out;          // Newton: psi_out += delta (nullable)
+    const int* active;        // per system (global index), nullable = all active
+    int* flags;               // per system, zero-pivot bit (nullable)
+    int* iters;               // per system, incremented on update (nullable)
+    void* wsC;                // [batch][I][NT][NT] factors (element type of the kernel)
+    void* wsY;                // [batch][I][NT]
+    long long sys0;           // first system of the batch
+    long long nsys;           // systems in the batch
+};
+
+hipError_t launch_setup(const double* e_edge, const double* nes_g, int N, Consts* out, hipStream_t st);
+
+hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, const double* psi_n,
+                           const double* psi, double* G_out, double g_sign, const ResidualOut& out,
+                           hipStream_t st);
+
+hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
+                         double* blocks, hipStream_t st);
+
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, hipStream_t st);
+
+hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
+                      const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,
+                      hipStream_t st);
+
+hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
+
+size_t factor_ws_bytes_per_system(int I, int N, bool fp32);
+int padded_groups(int N);
+
+}  // namespace tmk

@@ -1,0 +1,491 @@
+// FP64 zone-parallel kernels of libtm: grid constants, residual with per-system norms
+// and conservation sums, debug Jacobian blocks, and the adjoint vector-Jacobian product.
+//
+// Mapping: one 256-thread block per (species, ray) system; each thread owns whole
+// radial zones (strided), computes all N groups of a zone in registers, and the block
+// reduces per-system quantities in a fixed order (deterministic, no atomics).
+#include "tm_kernels.hpp"
+
+namespace tmk {
+
+// ---------------------------------------------------------------- grid constants
+
+__global__ void k_setup(const double* __restrict__ e_edge, const double* __restrict__ nes_g, int N,
+                        Consts* __restrict__ out) {
+    __shared__ double eps[kMaxN], W[kMaxN];
+    __shared__ double wbar;
+    const int t = threadIdx.x;
+    if (t < N) {
+        const double lo = e_edge[t], hi = e_edge[t + 1];
+        eps[t] = sqrt((hi * hi + hi * lo + lo * lo) * (1.0 / 3.0));   // eq. a01, square restored
+        W[t] = (hi - lo) * (hi * hi + hi * lo + lo * lo) * (1.0 / 3.0); // eq. a01b
+    }
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) s += W[k];
+        wbar = s / N;
+    }
+    __syncthreads();
+    if (t < kMaxN) {
+        out->eps[t] = t < N ? eps[t] : 0.0;
+        out->W[t] = t < N ? W[t] : 0.0;
+        out->de[t] = (t + 1 < N) ? eps[t + 1] - eps[t] : 0.0;
+    }
+    for (int idx = t; idx < kMaxN * kMaxN; idx += blockDim.x) {
+        const int k = idx / kMaxN, kp = idx % kMaxN;
+        double v = 0.0;
+        if (k < N && kp < N && nes_g != nullptr)
+            v = eps[k] * eps[kp] / (kEps0 * kEps0) * nes_g[k * N + kp] * (W[kp] / wbar);
+        out->P[k][kp] = v;
+    }
+}
+
+hipError_t launch_setup(const double* e_edge, const double* nes_g, int N, Consts* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, e_edge, nes_g, N, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- per-zone pieces
+
+// NES source of one zone: S_k = amp [(1 - p_k) sum_k' P Ein p_k' - p_k sum_k' P Eout (1 - p_k')]
+// with the detailed-balance factor exp(-|eps_k - eps_k'|/T) built as a product of
+// neighbour factors d_j = exp(-(eps_{j+1} - eps_j)/T) (Eout for k' > k, Ein for k' < k).
+// Also returns the two kernel sums (without amp) for the Jacobian diagonal.
+template <int NT>
+__device__ __forceinline__ void nes_zone(const Consts* __restrict__ cs, int N, double T, const double* p,
+                                         double* sin_out, double* sout_out) {
+    double d[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) d[j] = (j + 1 < N) ? exp(-cs->de[j] / T) : 0.0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        if (k >= N) break;
+        double sin_ = cs->P[k][k] * p[k];
+        double sout = cs->P[k][k] * (1.0 - p[k]);
+        double e = 1.0;
+#pragma unroll
+        for (int kp = k + 1; kp < NT; ++kp) {          // up-scatter side: out factor decays
+            if (kp >= N) break;
+            e *= d[kp - 1];
+            sout = fma(cs->P[k][kp] * e, 1.0 - p[kp], sout);
+            sin_ = fma(cs->P[k][kp], p[kp], sin_);
+        }
+        e = 1.0;
+#pragma unroll
+        for (int kp = k - 1; kp >= 0; --kp) {          // down-scatter side: in factor decays
+            e *= d[kp];
+            sin_ = fma(cs->P[k][kp] * e, p[kp], sin_);
+            sout = fma(cs->P[k][kp], 1.0 - p[kp], sout);
+        }
+        sin_out[k] = sin_;
+        sout_out[k] = sout;
+    }
+}
+
+struct ZoneGeom {
+    double V, A_lo, A_hi, D_lo, D_hi, V_lo, V_hi;
+};
+
+__device__ __forceinline__ ZoneGeom zone_geom(const double* __restrict__ re, int i, int I) {
+    ZoneGeom g;
+    const double rlo = re[i], rhi = re[i + 1];
+    g.V = shell_volume(rlo, rhi);
+    g.A_lo = rlo * rlo;
+    g.A_hi = rhi * rhi;
+    const double rc = 0.5 * (rlo + rhi);
+    g.D_lo = 0.0;
+    g.V_lo = 1.0;
+    g.D_hi = 0.0;
+    g.V_hi = 1.0;
+    if (i > 0) {
+        const double rm = re[i - 1];
+        g.D_lo = rc - 0.5 * (rm + rlo);
+        g.V_lo = shell_volume(rm, rlo);
+    }
+    if (i + 1 < I) {
+        const double rp = re[i + 2];
+        g.D_hi = 0.5 * (rhi + rp) - rc;
+        g.V_hi = shell_volume(rhi, rp);
+    }
+    return g;
+}
+
+__device__ __forceinline__ double inv_mfp(const Fields& f, size_t c) {
+    return 1.0 / (f.kappa_a[c] + f.eta[c] + f.kappa_s[c]);
+}
+
+// Block-wide deterministic reductions (fixed shuffle + LDS order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < kBlock / 64; ++j) s += sh[j];
+    return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+    for (int j = 1; j < kBlock / 64; ++j) s = fmax(s, sh[j]);
+    return s;
+}
+
+__device__ __forceinline__ int block_or(int v, double* sh) {
+    return block_max(v ? 1.0 : 0.0, sh) > 0.0 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- residual / statistics
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const Consts* __restrict__ cs,
+                                                     const double* __restrict__ psi_n,
+                                                     const double* __restrict__ psi, double* __restrict__ G_out,
+                                                     double g_sign, ResidualOut out) {
+    __shared__ double red[kBlock / 64];
+    const long long sys = blockIdx.x;
+    const int I = sh.I, N = sh.N;
+    const int ray = (int)(sys % sh.R);
+    const double* re = f.r_edge + (size_t)ray * (I + 1);
+    const double c = sh.c_dt;
+    const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+
+    double gmax = 0.0;
+    int bad = 0;
+    double s_n = 0.0, s_nold = 0.0, s_e = 0.0, s_q = 0.0, s_nes = 0.0, s_b = 0.0;
+
+    for (int i = threadIdx.x; i < I; i += kBlock) {
+        const size_t cb = ((size_t)sys * I + i) * N;
+        const ZoneGeom g = zone_geom(re, i, I);
+        double p[NT], G[NT], Hhi[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            p[k] = 0.0;
+            G[k] = 0.0;
+            Hhi[k] = 0.0;
+            if (k < N) {
+                p[k] = psi[cb + k];
+                G[k] = p[k] - psi_n[cb + k];
+            }
+        }
+        if (diff) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if (k >= N) break;
+                const double lam = inv_mfp(f, cb + k);
+                double Hlo = 0.0, Hh = 0.0;
+                if (i > 0) {
+                    const size_t cm = cb - N + k;
+                    const double lam_e = sqrt(lam * inv_mfp(f, cm));
+                    Hlo = edge_flux(psi[cm], p[k], lam_e, g.D_lo, sh.psi_floor, sh.limiter).H;
+                }
+                if (i + 1 < I) {
+                    const size_t cp = cb + N + k;
+                    const double lam_e = sqrt(lam * inv_mfp(f, cp));
+                    Hh = edge_flux(p[k], psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter).H;
+                } else if (sh.outer_bc == 1) {
+                    Hh = p[k];                                 // free streaming, eq. a22 limit
+                }
+                Hhi[k] = Hh;
+                G[k] += c * (g.A_hi * Hh - g.A_lo * Hlo) / g.V;
+            }
+        }
+        if (emabs) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if (k >= N) break;
+                G[k] += c * (f.kappa_a[cb + k] * p[k] - f.eta[cb + k] * (1.0 - p[k]));
+            }
+        }
+        double S[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) S[k] = 0.0;
+        if (nes) {
+            const double amp = f.nes_amp[(size_t)sys * I + i];
+            const double T = f.temp[(size_t)ray * I + i];
+            double si[NT], so[NT];
+            nes_zone<NT>(cs, N, T, p, si, so);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if (k >= N) break;
+                S[k] = amp * ((1.0 - p[k]) * si[k] - p[k] * so[k]);
+                G[k] -= c * S[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (k >= N) break;
+            const double a = fabs(G[k]);
+            bad |= !isfinite(G[k]);
+            gmax = fmax(gmax, a);
+            if (G_out) G_out[cb + k] = g_sign * G[k];
+        }
+        if (out.stats) {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if (k >= N) break;
+                const double vw = g.V * cs->W[k];
+                s_n = fma(vw, p[k], s_n);
+                s_nold = fma(vw, psi_n[cb + k], s_nold);
+                s_e = fma(vw * cs->eps[k], p[k], s_e);
+                if (emabs) s_q = fma(c * vw, f.eta[cb + k] * (1.0 - p[k]) - f.kappa_a[cb + k] * p[k], s_q);
+                if (nes) s_nes = fma(c * vw, S[k], s_nes);
+                if (i == I - 1 && diff) s_b = fma(cs->W[k], Hhi[k], s_b);
+            }
+        }
+    }
+
+    const double res = block_max(gmax, red);
+    bad = block_or(bad, red);
+    if (out.stats) {
+        s_n = block_sum(s_n, red);
+        s_nold = block_sum(s_nold, red);
+        s_e = block_sum(s_e, red);
+        s_q = block_sum(s_q, red);
+        s_nes = block_sum(s_nes, red);
+        s_b = block_sum(s_b, red);
+    }
+    if (threadIdx.x == 0) {
+        out.res[sys] = bad ? __builtin_nan("") : res;
+        double r0 = res;
+        if (out.set_res0 && out.res0) out.res0[sys] = bad ? __builtin_nan("") : res;
+        else if (out.res0) r0 = out.res0[sys];
+        const bool stop = !bad && res <= out.rtol * r0;          // Newton stopping rule
+        if (out.active) {
+            const int it = out.iters ? out.iters[sys] : 0;
+            out.active[sys] = (!stop && !bad && it < out.max_iter) ? 1 : 0;
+        }
+        if (out.flags) {
+            int fl = out.flags[sys] & 4;   // keep zero-pivot bit from the factorisation
+            if (out.rtol > 0.0 && !stop) fl |= 1;                  // rtol = 0: fixed count, no target
+            if (bad) fl |= 2;
+            out.flags[sys] = fl;
+        }
+        if (out.stats) {
+            const double rout = re[I] * re[I];
+            const double b = c * rout * s_b;
+            if (out.n_tot) out.n_tot[sys] = s_n;
+            if (out.e_tot) out.e_tot[sys] = s_e;
+            if (out.budget) out.budget[sys] = s_n - s_nold + b - s_q - s_nes;
+            if (out.lum) out.lum[sys] = kCLight * rout * s_b;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- debug Jacobian blocks
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_blocks(Shape sh, Fields f, const Consts* __restrict__ cs,
+                                                   const double* __restrict__ psi, double* __restrict__ blocks) {
+    const long long sys = blockIdx.x;
+    const int I = sh.I, N = sh.N;
+    const int ray = (int)(sys % sh.R);
+    const double* re = f.r_edge + (size_t)ray * (I + 1);
+    const double c = sh.c_dt;
+    for (int i = threadIdx.x; i < I; i += kBlock) {
+        const size_t cb = ((size_t)sys * I + i) * N;
+        const ZoneGeom g = zone_geom(re, i, I);
+        double p[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) p[k] = k < N ? psi[cb + k] : 0.0;
+        double si[NT], so[NT];
+        double amp = 0.0;
+        const bool nes = sh.terms & kNes;
+        if (nes) {
+            amp = f.nes_amp[(size_t)sys * I + i];
+            nes_zone<NT>(cs, N, f.temp[(size_t)ray * I + i], p, si, so);
+        }
+        double d[NT];
+        if (nes) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) d[j] = (j + 1 < N) ? exp(-cs->de[j] / f.temp[(size_t)ray * I + i]) : 0.0;
+        }
+        for (int k = 0; k < N; ++k) {
+            double* row = blocks + (cb + k) * (size_t)(N + 2);
+            double diag = 1.0, bm = 0.0, bp = 0.0;
+            if (sh.terms & kDiffusion) {
+                const double lam = inv_mfp(f, cb + k);
+                double dHv_lo = 0.0, dHu_lo = 0.0, dHu_hi = 0.0, dHv_hi = 0.0;
+                if (i > 0) {
+                    const size_t cm = cb - N + k;
+                    const EdgeFlux e = edge_flux(psi[cm], p[k], sqrt(lam * inv_mfp(f, cm)), g.D_lo,
+                                                 sh.psi_floor, sh.limiter);
+                    dHu_lo = e.dHu;
+                    dHv_lo = e.dHv;
+                }
+                if (i + 1 < I) {
+                    const size_t cp = cb + N + k;
+                    const EdgeFlux e = edge_flux(p[k], psi[cp], sqrt(lam * inv_mfp(f, cp)), g.D_hi,
+                                                 sh.psi_floor, sh.limiter);
+                    dHu_hi = e.dHu;
+                    dHv_hi = e.dHv;
+                } else if (sh.outer_bc == 1) {
+                    dHu_hi = 1.0;
+                }
+                diag += c * (g.A_hi * dHu_hi - g.A_lo * dHv_lo) / g.V;
+                bp = (i + 1 < I) ? c * g.A_hi * dHv_hi / g.V : 0.0;
+                bm = (i > 0) ? -c * g.A_lo * dHu_lo / g.V : 0.0;
+            }
+            if (sh.terms & kEmAbs) diag += c * (f.eta[cb + k] + f.kappa_a[cb + k]);
+            const double pk = p[k];
+            for (int kp = 0; kp < N; ++kp) {
+                double v = 0.0;
+                if (nes) {
+                    // detailed-balance factor exp(-|eps_k - eps_k'|/T) as a neighbour product
+                    double e = 1.0;
+                    for (int j = min(k, kp); j < max(k, kp); ++j) e *= d[j];
+                    const double kout = amp * cs->P[k][kp] * (kp > k ? e : 1.0);
+                    const double kin = amp * cs->P[k][kp] * (kp < k ? e : 1.0);
+                    v = -c * ((1.0 - pk) * kin + pk * kout);
+                }
+                row[kp] = v;
+            }
+            if (nes) diag += c * amp * (si[k] + so[k]);
+            row[k] += diag;
+            row[N] = bm;
+            row[N + 1] = bp;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- adjoint VJP
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts* __restrict__ cs,
+                                                const double* __restrict__ psi, const double* __restrict__ mu,
+                                                double* g_ka, double* g_eta, double* g_ks, double* g_amp) {
+    const long long sys = blockIdx.x;
+    const int I = sh.I, N = sh.N;
+    const int ray = (int)(sys % sh.R);
+    const double* re = f.r_edge + (size_t)ray * (I + 1);
+    const double c = sh.c_dt;
+    const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+    for (int i = threadIdx.x; i < I; i += kBlock) {
+        const size_t cb = ((size_t)sys * I + i) * N;
+        const ZoneGeom g = zone_geom(re, i, I);
+        double p[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) p[k] = k < N ? psi[cb + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (k >= N) break;
+            const double lam = inv_mfp(f, cb + k);
+            const double m0 = mu[cb + k];
+            double gchi = 0.0;     // sum over the two edges of (mu-weighted dG/dH) dH/dlam dlam/dchi
+            if (diff) {
+                if (i + 1 < I) {
+                    const size_t cp = cb + N + k;
+                    const double lam_e = sqrt(lam * inv_mfp(f, cp));
+                    const EdgeFlux e = edge_flux(p[k], psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter);
+                    const double w = c * g.A_hi * (m0 / g.V - mu[cp] / g.V_hi);
+                    gchi += w * e.dHlam * (-0.5 * lam_e * lam);
+                }
+                if (i > 0) {
+                    const size_t cm = cb - N + k;
+                    const double lam_e = sqrt(lam * inv_mfp(f, cm));
+                    const EdgeFlux e = edge_flux(psi[cm], p[k], lam_e, g.D_lo, sh.psi_floor, sh.limiter);
+                    const double w = c * g.A_lo * (mu[cm] / g.V_lo - m0 / g.V);
+                    gchi += w * e.dHlam * (-0.5 * lam_e * lam);
+                }
+            }
+            double gka = gchi, geta = gchi;
+            if (emabs) {
+                gka += m0 * c * p[k];
+                geta -= m0 * c * (1.0 - p[k]);
+            }
+            if (g_ka) g_ka[cb + k] = -gka;
+            if (g_eta) g_eta[cb + k] = -geta;
+            if (g_ks) g_ks[cb + k] = -gchi;
+        }
+        if (g_amp) {
+            double ga = 0.0;
+            if (nes) {
+                double si[NT], so[NT];
+                nes_zone<NT>(cs, N, f.temp[(size_t)ray * I + i], p, si, so);
+#pragma unroll
+                for (int k = 0; k < NT; ++k) {
+                    if (k >= N) break;
+                    const double s1 = (1.0 - p[k]) * si[k] - p[k] * so[k];
+                    ga = fma(mu[cb + k] * c, s1, ga);
+                }
+            }
+            g_amp[(size_t)sys * I + i] = ga;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- active-system count
+
+__global__ __launch_bounds__(kBlock) void k_count(const int* __restrict__ active, long long n, int* count) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (long long j = threadIdx.x; j < n; j += kBlock) s += active[j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *count = (int)s;
+}
+
+hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, st, active, n, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dispatch on the padded group count
+
+int padded_groups(int N) {
+    static const int sizes[] = {4, 8, 12, 16, 20, 24, 28, 32};
+    for (int s : sizes)
+        if (N <= s) return s;
+    return -1;
+}
+
+#define TM_DISPATCH_NT(NTV, ...)                                       \
+    switch (NTV) {                                                     \
+        case 4: { constexpr int NT = 4; __VA_ARGS__; } break;          \
+        case 8: { constexpr int NT = 8; __VA_ARGS__; } break;          \
+        case 12: { constexpr int NT = 12; __VA_ARGS__; } break;        \
+        case 16: { constexpr int NT = 16; __VA_ARGS__; } break;        \
+        case 20: { constexpr int NT = 20; __VA_ARGS__; } break;        \
+        case 24: { constexpr int NT = 24; __VA_ARGS__; } break;        \
+        case 28: { constexpr int NT = 28; __VA_ARGS__; } break;        \
+        case 32: { constexpr int NT = 32; __VA_ARGS__; } break;        \
+        default: return hipErrorInvalidValue;                          \
+    }
+
+hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, const double* psi_n,
+                           const double* psi, double* G_out, double g_sign, const ResidualOut& out,
+                           hipStream_t st) {
+    const long long nsys = (long long)sh.S * sh.R;
+    TM_DISPATCH_NT(padded_groups(sh.N),
+                   hipLaunchKernelGGL(k_residual<NT>, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f, cs,
+                                      psi_n, psi, G_out, g_sign, out));
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi, double* blocks,
+                         hipStream_t st) {
+    const long long nsys = (long long)sh.S * sh.R;
+    TM_DISPATCH_NT(padded_groups(sh.N),
+                   hipLaunchKernelGGL(k_blocks<NT>, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f, cs, psi,
+                                      blocks));
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi, const double* mu,
+                      double* g_ka, double* g_eta, double* g_ks, double* g_amp, hipStream_t st) {
+    const long long nsys = (long long)sh.S * sh.R;
+    TM_DISPATCH_NT(padded_groups(sh.N),
+                   hipLaunchKernelGGL(k_vjp<NT>, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f, cs, psi, mu,
+                                      g_ka, g_eta, g_ks, g_amp));
+    return hipGetLastError();
+}
+
+}  // namespace tmk

@@ -1,0 +1,275 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Metric for states: err = max |x - x_ref| / max(|x_ref|, tau), tau = 1e-30, which keeps
+cells whose occupation underflows FP32 meaningful (two independent FP64 routes of the
+oracle agree to about 2e-16 under this metric).  Bars: FP64 path 1e-12, mixed path 1e-8.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1809_05608_amd import tm
+
+pytestmark = pytest.mark.gpu
+TAU = 1e-30
+FP64_BAR = 1e-12
+MIXED_BAR = 1e-8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, ref):
+    return float(np.max(np.abs(a - ref) / np.maximum(np.abs(ref), TAU)))
+
+
+def _ctx(wd, precision=tm.PREC_FP64):
+    return tm.Context(tm.problem_of(wd, precision)), tm.DeviceFields.of(wd)
+
+
+def gpu_newton(w, max_iter, rtol, precision=tm.PREC_FP64, raise_on_status=False):
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd, precision)
+    psi = wd.psi_n.clone()
+    st, stats = ctx.newton_step(f, wd.psi_n, psi, max_iter, rtol, raise_on_status=raise_on_status)
+    torch.cuda.synchronize()
+    return st, psi.cpu().numpy(), {k: v.cpu().numpy() for k, v in stats.items()}
+
+
+def oracle_newton(w, max_iter, rtol, systems=None):
+    return oracle.newton_batch(w.numpy(), max_iter=max_iter, rtol=rtol, systems=systems)
+
+
+RAGGED = [
+    dict(S=1, R=3, I=1, N=1),      # single zone, single group
+    dict(S=2, R=3, I=37, N=13),    # padded groups (16), odd systems per block
+    dict(S=1, R=5, I=19, N=20),
+    dict(S=1, R=2, I=9, N=32),     # maximum group count
+    dict(S=3, R=1, I=2, N=5),
+]
+
+
+# ------------------------------------------------------------------ residual and blocks
+
+@pytest.mark.parametrize("shape", [dict(S=1, R=16, I=64, N=12)] + RAGGED)
+def test_residual_and_blocks_match_oracle(shape):
+    say("case residual/blocks", shape)
+    w = synth.make_custom(**shape)
+    rng = np.random.default_rng(11)
+    psi = (w.psi_n.numpy() * rng.uniform(0.7, 1.3, w.psi_n.shape)).clip(0, 1)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd)
+    psi_d = torch.as_tensor(psi, device="cuda")
+    G = torch.empty_like(psi_d)
+    B = torch.empty(tuple(psi_d.shape) + (w.N + 2,), dtype=torch.float64, device="cuda")
+    ctx.assemble(f, wd.psi_n, psi_d, G, B)
+    torch.cuda.synchronize()
+    G, B = G.cpu().numpy(), B.cpu().numpy()
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    for s in range(w.S):
+        for r in range(w.R):
+            Go = oracle.residual(syss[s][r], wn["psi_n"][s, r], psi[s, r])
+            np.testing.assert_allclose(G[s, r], Go, rtol=1e-11, atol=1e-13)
+            A, bm, bp = oracle.jacobian_blocks(syss[s][r], psi[s, r])
+            scale = np.max(np.abs(A), axis=2, keepdims=True)
+            np.testing.assert_allclose(B[s, r, :, :, :w.N], A, rtol=0, atol=1e-12 * scale.max())
+            np.testing.assert_allclose(B[s, r, :, :, w.N], bm, rtol=1e-11, atol=1e-14 * scale.max())
+            np.testing.assert_allclose(B[s, r, :, :, w.N + 1], bp, rtol=1e-11, atol=1e-14 * scale.max())
+
+
+# ------------------------------------------------------------------ linear solves
+
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("precision", [tm.PREC_FP64, tm.PREC_MIXED])
+@pytest.mark.parametrize("shape", [dict(S=1, R=16, I=64, N=12)] + RAGGED)
+def test_factor_solve_matches_oracle(shape, precision, transpose):
+    say("case factor_solve", shape, "prec", precision, "T", transpose)
+    w = synth.make_custom(**shape)
+    rng = np.random.default_rng(12)
+    psi = w.psi_n.numpy() * 1.05
+    rhs = rng.standard_normal(psi.shape)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd, precision)
+    x = torch.empty(psi.shape, dtype=torch.float64, device="cuda")
+    ctx.factor_solve(f, torch.as_tensor(psi, device="cuda"), torch.as_tensor(rhs, device="cuda"), x, transpose)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    bar = 1e-11 if precision == tm.PREC_FP64 else 3e-4
+    for s in range(w.S):
+        for r in range(w.R):
+            A, bm, bp = oracle.jacobian_blocks(syss[s][r], psi[s, r])
+            xo = oracle.block_thomas_solve(A, bm, bp, rhs[s, r], transpose=transpose)
+            err = np.max(np.abs(x[s, r] - xo)) / np.max(np.abs(xo))
+            assert err < bar, (s, r, err)
+
+
+# ------------------------------------------------------------------ Newton step
+
+def test_newton_cfg0_three_iterations_fp64():
+    """16 rays x 64 zones x 12 groups, exactly 3 Newton updates."""
+    say("case newton cfg0")
+    w = synth.make(0)
+    st, psi, stats = gpu_newton(w, 3, 0.0)
+    assert st == 0, tm.STATUS_NAMES[st]
+    ref, info = oracle_newton(w, 3, 0.0)
+    assert rel_err(psi, ref) < FP64_BAR
+    assert np.all(stats["iters"] == 3) and np.all(stats["flags"] == 0)
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    for r in range(w.R):
+        so = oracle.step_stats(syss[0][r], wn["psi_n"][0, r], ref[0, r])
+        np.testing.assert_allclose(stats["n_tot"][r], so["n_tot"], rtol=1e-12)
+        np.testing.assert_allclose(stats["e_tot"][r], so["e_tot"], rtol=1e-12)
+        np.testing.assert_allclose(stats["lum_n"][r], so["lum_n"], rtol=1e-11)
+        np.testing.assert_allclose(stats["budget_n"][r], so["budget"], rtol=1e-6, atol=1e-9 * abs(so["n_tot"]))
+        np.testing.assert_allclose(stats["res0_inf"][r], info[(0, r)].res0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+def test_newton_ragged_shapes_fp64(shape):
+    say("case newton ragged", shape)
+    w = synth.make_custom(**shape)
+    st, psi, stats = gpu_newton(w, 4, 0.0)
+    assert st == 0
+    ref, _ = oracle_newton(w, 4, 0.0)
+    assert rel_err(psi, ref) < FP64_BAR
+
+
+def test_newton_to_tolerance_cfg1_sampled_rays():
+    """Four species on sampled rays of the 180-ray configuration, Newton to 1e-10 relative residual:
+    the same per-system iteration counts and states as the oracle."""
+    say("case newton cfg1 rays")
+    w = synth.make(1, rays=[0, 97, 179])
+    st, psi, stats = gpu_newton(w, 30, 1e-10)
+    assert st == 0, tm.STATUS_NAMES[st]
+    ref, info = oracle_newton(w, 30, 1e-10)
+    assert rel_err(psi, ref) < FP64_BAR
+    for (s, r), res in info.items():
+        assert stats["iters"][s * w.R + r] == res.iters
+
+
+@pytest.mark.parametrize("terms,limiter,outer_bc", [(1, 1, 0), (1, 0, 1), (2, 1, 1), (4 | 1, 1, 0), (7, 0, 0)])
+def test_newton_term_subsets(terms, limiter, outer_bc):
+    say("case terms", terms, limiter, outer_bc)
+    w = dataclasses.replace(synth.make_custom(S=2, R=3, I=24, N=10), terms=terms, limiter=limiter, outer_bc=outer_bc)
+    st, psi, _ = gpu_newton(w, 3, 0.0)
+    ref, _ = oracle_newton(w, 3, 0.0)
+    assert rel_err(psi, ref) < FP64_BAR
+
+
+def test_mixed_precision_refines_to_fp64_answer():
+    """Mixed path (FP32 factorisation, FP64 residual/update) on rays of the spiked
+    4096-ray configuration including opacity-spike rays: within 1e-8 of the FP64 oracle."""
+    ids, _, _ = synth.workload._spikes(2, 4096, 540)
+    rays = [int(ids[0]), int(ids[1]), 5]
+    say("case mixed cfg2 rays", rays)
+    w = synth.make(2, rays=rays)
+    st, psi, stats = gpu_newton(w, 30, 1e-12, precision=tm.PREC_MIXED)
+    assert st == 0, tm.STATUS_NAMES[st]
+    ref, info = oracle_newton(w, 30, 1e-12)
+    assert rel_err(psi, ref) < MIXED_BAR
+    assert np.all(stats["res_inf"] <= 1e-12 * stats["res0_inf"])
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _adjoint_workload():
+    w = synth.make_custom(S=1, R=3, I=12, N=6)
+    return dataclasses.replace(w, kappa_a=w.kappa_a * 30, eta=w.eta * 30, kappa_s=w.kappa_s * 30,
+                               nes_amp=w.nes_amp * 300)
+
+
+def test_adjoint_matches_oracle():
+    say("case adjoint")
+    w = _adjoint_workload()
+    ref, _ = oracle_newton(w, 40, 1e-14)
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd)
+    psi = torch.as_tensor(ref, device="cuda")
+    seed = np.zeros_like(ref)
+    for r in range(w.R):
+        seed[0, r] = oracle.luminosity_seed(syss[0][r], ref[0, r].shape)
+    seed_d = torch.as_tensor(seed, device="cuda")
+    mu = torch.empty_like(psi)
+    g = {n: torch.empty_like(psi) for n in ("kappa_a", "eta", "kappa_s")}
+    gamp = torch.empty(w.S, w.R, w.I, dtype=torch.float64, device="cuda")
+    ctx.adjoint_step(f, wd.psi_n, psi, seed_d, mu, g["kappa_a"], g["eta"], g["kappa_s"], gamp)
+    torch.cuda.synchronize()
+    for r in range(w.R):
+        mo = oracle.adjoint(syss[0][r], ref[0, r], seed[0, r])
+        go = oracle.param_vjp(syss[0][r], ref[0, r], mo)
+        sc = np.max(np.abs(mo))
+        np.testing.assert_allclose(mu[0, r].cpu().numpy(), mo, rtol=1e-10, atol=1e-12 * sc)
+        for n in g:
+            gs = np.max(np.abs(go[n]))
+            np.testing.assert_allclose(g[n][0, r].cpu().numpy(), go[n], rtol=1e-9, atol=1e-11 * gs)
+        np.testing.assert_allclose(gamp[0, r].cpu().numpy(), go["nes_amp"], rtol=1e-9,
+                                   atol=1e-11 * np.max(np.abs(go["nes_amp"])))
+
+
+def test_transport_step_autograd_matches_oracle_gradient():
+    say("case autograd")
+    w = _adjoint_workload()
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd)
+    ka = wd.kappa_a.clone().requires_grad_(True)
+    et = wd.eta.clone().requires_grad_(True)
+    pn = wd.psi_n.clone().requires_grad_(True)
+    psi = tm.TransportStep.apply(ka, et, wd.kappa_s, pn, ctx, f, 40, 1e-14)
+    wl = tm.luminosity_weights(wd)                             # [R][N]
+    L = (psi[:, :, -1, :] * wl[None]).sum()
+    L.backward()
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    ref, _ = oracle_newton(w, 40, 1e-14)
+    for r in range(w.R):
+        seed = oracle.luminosity_seed(syss[0][r], ref[0, r].shape)
+        mo = oracle.adjoint(syss[0][r], ref[0, r], seed)
+        go = oracle.param_vjp(syss[0][r], ref[0, r], mo)
+        for name, t in (("kappa_a", ka), ("eta", et), ("psi_n", pn)):
+            np.testing.assert_allclose(t.grad[0, r].cpu().numpy(), go[name], rtol=1e-8,
+                                       atol=1e-10 * np.max(np.abs(go[name])))
+
+
+# ------------------------------------------------------------------ failure handling (forced from the host)
+
+def test_nonfinite_input_is_reported():
+    say("case nonfinite")
+    w = synth.make_custom(S=1, R=4, I=8, N=6)
+    ka = w.kappa_a.clone()
+    ka[0, 2, 3, 1] = float("nan")
+    w = dataclasses.replace(w, kappa_a=ka)
+    st, _, stats = gpu_newton(w, 3, 1e-10)
+    assert st == 5                                  # TM_ERR_NONFINITE
+    assert stats["flags"][2] & tm.FLAG_NONFINITE
+    assert not np.any(stats["flags"][[0, 1, 3]] & tm.FLAG_NONFINITE)
+
+
+def test_iteration_cap_is_reported():
+    say("case not converged")
+    w = synth.make_custom(S=1, R=2, I=8, N=6)
+    st, _, stats = gpu_newton(w, 1, 1e-30)
+    assert st == 4                                  # TM_ERR_NOT_CONVERGED
+    assert np.all(stats["flags"] & tm.FLAG_NOT_CONVERGED) and np.all(stats["iters"] == 1)
+
+
+def test_binding_rejects_bad_tensors():
+    say("case binding checks")
+    w = synth.make_custom(S=1, R=2, I=8, N=6).to("cuda")
+    ctx, f = _ctx(w)
+    with pytest.raises(ValueError):
+        ctx.newton_step(f, w.psi_n, w.psi_n.float(), 1, 0.0)
+    with pytest.raises(ValueError):
+        ctx.newton_step(f, w.psi_n, w.psi_n[:, :1].clone(), 1, 0.0)

@@ -193,10 +193,22 @@ def nes_source(sys: System, psi: np.ndarray, unit_amplitude: bool = False):
     S = np.zeros((I, N))
     for i in range(I):
         amp = 1.0 if unit_amplitude else sys.nes_amp[i]
-        k_out, k_in = nes_kernels(amp, sys.temp[i], eps, W, sys.nes_g)
+        k_out, k_in = _off_diagonal(*nes_kernels(amp, sys.temp[i], eps, W, sys.nes_g))
         p = psi[i]
         S[i] = (1.0 - p) * (k_in @ p) - p * (k_out @ (1.0 - p))
     return S
+
+
+def _off_diagonal(*kernels):
+    """Kernels without the k' = k terms.  Scattering that keeps the energy group has no
+    zeroth-moment source (eq. d8b): its in and out terms cancel identically, so they are
+    left out rather than summed and cancelled in floating point."""
+    out = []
+    for K in kernels:
+        K = K.copy()
+        np.fill_diagonal(K, 0.0)
+        out.append(K)
+    return out
 
 
 # ---------------------------------------------------------------- residual and Jacobian
@@ -247,7 +259,7 @@ def jacobian_blocks(sys: System, psi: np.ndarray):
     for i in range(I):
         blocks[i][np.diag_indices(N)] = diag[i]
         if sys.terms & TERM_NES:
-            k_out, k_in = nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g)
+            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g))
             p = psi[i]
             # -c dS_k/dpsi_m : dense part for every m (the m = k term included) ...
             blocks[i] -= c * ((1.0 - p)[:, None] * k_in + p[:, None] * k_out)

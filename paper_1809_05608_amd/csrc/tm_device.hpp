@@ -16,7 +16,8 @@ constexpr int kBlock = 256;                    // threads per block for every ke
 //   W[k]    phase-space weight (eq. a01b)
 //   de[k]   eps[k+1] - eps[k]
 //   P[k][k'] = (eps_k eps_k' / eps0^2) nes_g[k][k'] W_k' / mean(W)   (NES kernel without amplitude
-//              and without the detailed-balance factor)
+//              and without the detailed-balance factor); P[k][k] = 0 because scattering within a
+//              group has no zeroth-moment source (its in and out terms cancel identically)
 struct Consts {
     double eps[kMaxN];
     double W[kMaxN];

@@ -35,7 +35,8 @@ __global__ void k_setup(const double* __restrict__ e_edge, const double* __restr
     for (int idx = t; idx < kMaxN * kMaxN; idx += blockDim.x) {
         const int k = idx / kMaxN, kp = idx % kMaxN;
         double v = 0.0;
-        if (k < N && kp < N && nes_g != nullptr)
+        // k' = k (no energy change) is left out: its in and out terms cancel identically (eq. d8b)
+        if (k < N && kp < N && kp != k && nes_g != nullptr)
             v = eps[k] * eps[kp] / (kEps0 * kEps0) * nes_g[k * N + kp] * (W[kp] / wbar);
         out->P[k][kp] = v;
     }
@@ -61,8 +62,8 @@ __device__ __forceinline__ void nes_zone(const Consts* __restrict__ cs, int N, d
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
         if (k >= N) break;
-        double sin_ = cs->P[k][k] * p[k];
-        double sout = cs->P[k][k] * (1.0 - p[k]);
+        double sin_ = 0.0;
+        double sout = 0.0;
         double e = 1.0;
 #pragma unroll
         for (int kp = k + 1; kp < NT; ++kp) {          // up-scatter side: out factor decays

@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the implicit ray-by-ray MGFLD transport step on one MI355X.
+
+Workload: 16384 rays x 540 zones x 20 groups x 4 species (707,788,800 cells), the
+synthetic stellar-profile recipe of `synth`, generated directly in HBM.  One bench
+step = one implicit time step: the mixed-precision Newton iteration (FP32 block
+factorisation, FP64 residual/update/sums) refined to a 1e-12 relative residual.
+Alongside, the FP64 path is timed to the same tolerance (time-to-tolerance and the
+mixed-vs-FP64 error are reported), and the FP64 adjoint of the outer luminosity.
+
+Metric: Newton updates/s = sum over systems of (Newton updates applied) x I x N / time.
+Output: one JSON line on stdout (progress goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray·zone·group Newton updates/s, mixed vs FP64 at ≤1e-8 rel err; % roofline"
+TAU = 1e-30
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz without packed-FP32 math
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.6, FP64 and non-packed FP32 VALU
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def factor_flops_per_cell(N: int) -> float:
+    """Algorithmic flops per cell per Newton iteration: 2N^2 + 20N (block inverse dominant)."""
+    return 2.0 * N * N + 20.0 * N
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_record(kernel_src):
+    """HBM traffic per launch measured with rocprofv3 --pmc, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_factor_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256_16") != source_hash(kernel_src):
+        return None
+    return rec
+
+
+def rel_err_gpu(a, ref):
+    import torch
+    return float(torch.max((a - ref).abs() / ref.abs().clamp_min(TAU)).item())
+
+
+def run_newton_leg(tm, torch, w, f, precision, steps, warmup, rtol, max_iter):
+    ctx = tm.Context(tm.problem_of(w, precision))
+    psi = torch.empty_like(w.psi_n)
+    cells_per_sys = w.I * w.N
+    times, updates = [], []
+    stats = None
+    for s in range(warmup + steps):
+        psi.copy_(w.psi_n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stats = ctx.newton_step(f, w.psi_n, psi, max_iter, rtol, with_stats=True, raise_on_status=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if st != 0:
+            log("newton status", tm.STATUS_NAMES.get(st, st))
+        it = stats["iters"].to(torch.int64)
+        if s >= warmup:
+            times.append(t1 - t0)
+            updates.append(int(it.sum().item()) * cells_per_sys)
+        log(f"  {'warm' if s < warmup else 'step'} {s}: {1e3 * (t1 - t0):.1f} ms, iters "
+            f"min {int(it.min())} max {int(it.max())}, status {tm.STATUS_NAMES.get(st, st)}")
+    return ctx, psi, stats, times, updates
+
+
+def time_kernel(torch, fn, reps):
+    """Average duration of `fn` (one kernel launch plus trivial setup) with HIP events on the current stream."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    fn()
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps / 1e3
+
+
+def cpu_baseline(sample_systems: int, workers: int):
+    """The FP64 oracle (as written, untuned) on a bounded sample of systems of the same workload."""
+    import multiprocessing as mp
+    import numpy as np
+    import synth
+    rays = list(range(0, 16384, 16384 // max(1, sample_systems // 4)))[: max(1, sample_systems // 4)]
+    w = synth.make(4, rays=rays, device="cpu").numpy()
+    jobs = [(s, r) for r in range(len(rays)) for s in range(4)][:sample_systems]
+    args = []
+    for s, r in jobs:
+        one = {k: (v[s:s + 1, r:r + 1] if k in ("kappa_a", "eta", "kappa_s", "psi_n") else
+                   v[s:s + 1, r:r + 1] if k == "nes_amp" else v[r:r + 1] if k in ("r_edge", "temp") else v)
+               for k, v in w.items()}
+        one.update(S=1, R=1)
+        args.append(one)
+    # one single-threaded worker process per core (fresh interpreters: no inherited thread pools)
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            pool.map(_noop, range(workers))            # interpreter start-up outside the timed region
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_one, args, chunksize=1)
+            dt = time.perf_counter() - t0
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    upd = sum(it for it in res) * w["I"] * w["N"]
+    return upd / dt, dt, len(jobs), upd
+
+
+def _noop(_):
+    import oracle  # noqa: F401
+    return 0
+
+
+def _oracle_one(w):
+    import oracle
+    sysm = oracle.systems_from_workload(w)[0][0]
+    return oracle.newton(sysm, w["psi_n"][0, 0], max_iter=30, rtol=1e-12).iters
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-12)
+    ap.add_argument("--max-iter", type=int, default=30)
+    ap.add_argument("--rays", type=int, default=16384, help="rays of the 16384-ray workload to use")
+    ap.add_argument("--kernel-reps", type=int, default=3)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested); the transport systems of a "
+              "multi-GPU run would be sharded by ray with no exchange inside a step", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_1809_05608_amd import tm
+
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    log("generating inputs in HBM")
+    rays = None if a.rays >= 16384 else range(a.rays)
+    w = synth.make(4, rays=rays, device=dev)
+    f = tm.DeviceFields.of(w)
+    torch.cuda.synchronize()
+    cells = w.n_cells
+    log(f"workload {w.name}: {w.S}x{w.R}x{w.I}x{w.N} = {cells} cells")
+
+    # ---------------- mixed-precision leg (headline)
+    log("mixed-precision Newton")
+    ctx_m, psi_m, st_m, t_m, u_m = run_newton_leg(tm, torch, w, f, tm.PREC_MIXED, a.steps, a.warmup, a.rtol,
+                                                  a.max_iter)
+    mixed_iters = st_m["iters"].to(torch.float64)
+    # dominant kernel: the FP32 fused assembly + block-Thomas factor/solve, one launch per call
+    G = torch.empty_like(psi_m)
+    ctx_m.assemble(f, w.psi_n, w.psi_n, G)
+    x = torch.empty_like(psi_m)
+    t_fac = time_kernel(torch, lambda: ctx_m.factor_solve(f, w.psi_n, G, x), a.kernel_reps)
+    t_res = time_kernel(torch, lambda: ctx_m.assemble(f, w.psi_n, w.psi_n, G), a.kernel_reps)
+    del G, x
+    ctx_m.close()
+    torch.cuda.empty_cache()
+
+    out_fp64 = None
+    out_adj = None
+    err_mixed = None
+    if not a.no_fp64:
+        log("FP64 Newton")
+        ctx_d, psi_d, st_d, t_d, u_d = run_newton_leg(tm, torch, w, f, tm.PREC_FP64, a.steps, a.warmup, a.rtol,
+                                                      a.max_iter)
+        err_mixed = rel_err_gpu(psi_m, psi_d)
+        xs = torch.empty_like(psi_d)
+        t_fac64 = time_kernel(torch, lambda: ctx_d.factor_solve(f, w.psi_n, psi_m, xs), 1)
+        del xs
+        out_fp64 = dict(value=sum(u_d) / sum(t_d), ms_per_step=1e3 * sum(t_d) / len(t_d),
+                        mean_iters=float(st_d["iters"].double().mean()), factor_kernel_ms=1e3 * t_fac64)
+        if not a.no_adjoint:
+            log("FP64 adjoint")
+            seed = torch.empty_like(psi_d)
+            ctx_d.luminosity_seed(f, seed)
+            mu = torch.empty_like(psi_d)
+            g = [torch.empty_like(psi_d) for _ in range(3)]
+            gamp = torch.empty_like(w.nes_amp)
+            tadj = time_kernel(torch, lambda: ctx_d.adjoint_step(f, w.psi_n, psi_d, seed, mu, *g, gamp),
+                               max(1, a.steps))
+            out_adj = dict(ms_per_step=1e3 * tadj, finite=bool(torch.isfinite(g[0]).all().item()))
+            del seed, mu, g, gamp
+        ctx_d.close()
+        del psi_d
+        torch.cuda.empty_cache()
+
+    value = sum(u_m) / sum(t_m)
+    ms = 1e3 * sum(t_m) / len(t_m)
+    flops_launch = factor_flops_per_cell(w.N) * cells
+    achieved = flops_launch / t_fac / 1e12
+    kernel_src = os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_factor.hip")
+    tr = traffic_record(kernel_src)
+    roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                frac=achieved / PEAK_VALU_TFLOPS, traffic=(tr or {}).get("bytes_per_launch"),
+                kernel="k_factor<float,20,false>", kernel_ms=1e3 * t_fac,
+                flops_per_launch=flops_launch, residual_kernel_ms=1e3 * t_res)
+
+    cpu = None
+    if not a.no_cpu:
+        log("CPU oracle baseline")
+        workers = min(16, os.cpu_count() or 1)
+        v, dt, nsys, upd = cpu_baseline(a.cpu_sample, workers)
+        cpu = dict(value=v, unit="updates/s", cores=workers, kind="oracle",
+                   sample=f"{nsys} systems (species x rays spread over the 16384 rays) of the same workload, "
+                          f"FP64 Newton to 1e-12, {upd} updates in {dt:.1f} s wall")
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 factor + f64 residual", "data": "synthetic",
+        "config": {"workload": f"{w.name}: one implicit step, mixed precision Newton to rtol {a.rtol:g}",
+                   "rays": w.R, "zones": w.I, "groups": w.N, "species": w.S, "cells": cells,
+                   "mean_newton_iters": float(mixed_iters.mean())},
+        "mixed_err_vs_fp64": err_mixed,
+        "fp64": out_fp64,
+        "mixed_vs_fp64_speedup": (out_fp64["ms_per_step"] / ms) if out_fp64 else None,
+        "adjoint_fp64": out_adj,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

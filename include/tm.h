@@ -166,8 +166,12 @@ tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
 /* Backward-Euler Newton iteration (eq. a62aa) for psi^{n+1} of every system.
  * psi holds the initial guess on entry (usually a copy of psi_n) and psi^{n+1} on
  * return.  Per system, an update J delta = -G is applied while
- * max|G(psi)| > rtol * max|G(psi_initial)| and fewer than max_iter updates have
- * been made (rtol = 0 runs exactly max_iter updates).  `stats` (all pointers
+ *   max|G(psi)| > max(rtol * max|G(psi_initial)|, g_round)
+ * and fewer than max_iter updates have been made, where g_round = 32 * 2^-52 * the
+ * largest sum over a cell of the magnitudes of the terms of G (the level below which
+ * G itself is rounding).  rtol = 0 runs exactly max_iter updates (unless G is exactly
+ * zero).  In TM_PREC_MIXED each update is an FP32 solve of the FP64 residual, so the
+ * iteration is iterative refinement to the same stopping rule.  `stats` (all pointers
  * device, may be NULL as a whole) receives the per-system results at the returned
  * psi.  Returns TM_OK, or the worst of TM_ERR_NONFINITE, TM_ERR_SINGULAR,
  * TM_ERR_NOT_CONVERGED over systems (per-system detail in stats.flags).           */
@@ -183,6 +187,12 @@ tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
                           const double *psi_np1, const double *seed, double *mu,
                           double *g_kappa_a, double *g_eta, double *g_kappa_s,
                           double *g_nes_amp);
+
+/* Seed of the adjoint for the outer-boundary number luminosity
+ *   L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}   (number through the outer surface, eq. a62)
+ * written as a cell array: dL_N/dpsi = c R_{I+1/2}^2 W_k in the outermost zone, zero
+ * elsewhere (zero everywhere without an outgoing flux).  Needs r_edge and e_edge only. */
+tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, double *seed);
 
 /* Human-readable name of a status code (static storage).                          */
 const char *tm_status_string(tm_status status);

@@ -356,7 +356,7 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
         hist.append(r)
         if res0 is None:
             res0 = r
-        if r <= rtol * res0:
+        if r == 0.0 or (rtol > 0.0 and r <= max(rtol * res0, residual_rounding_level(sys, psi_n, psi))):
             break
         blocks, bm, bp = jacobian_blocks(sys, psi)
         psi = psi + block_thomas_solve(blocks, bm, bp, -G)
@@ -366,7 +366,31 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
     if res0 is None:
         res0 = r
     hist.append(r)
-    return NewtonResult(psi=psi, iters=iters, res0=res0, res=r, converged=bool(r <= rtol * res0), history=hist)
+    conv = r <= max(rtol * res0, residual_rounding_level(sys, psi_n, psi)) if rtol > 0.0 else True
+    return NewtonResult(psi=psi, iters=iters, res0=res0, res=r, converged=bool(conv), history=hist)
+
+
+def residual_rounding_level(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> float:
+    """32 ulp of the largest per-cell sum of the magnitudes of the terms of G.
+
+    G is a sum of terms that nearly cancel near the solution; below this level the
+    computed residual is rounding, so the stopping rule asks for no progress beyond it.
+    """
+    _, V, A, _ = geometry(sys.r_edge)
+    c = sys.c_dt
+    mag = np.abs(psi) + np.abs(psi_n)
+    if sys.terms & TERM_DIFFUSION:
+        H = _edge_fluxes(sys, psi)[0]
+        mag = mag + c * (np.abs(A[1:, None] * H[1:]) + np.abs(A[:-1, None] * H[:-1])) / V[:, None]
+    if sys.terms & TERM_EMABS:
+        mag = mag + c * (np.abs(sys.kappa_a * psi) + np.abs(sys.eta * (1.0 - psi)))
+    if sys.terms & TERM_NES:
+        eps, W = group_energies(sys.e_edge)
+        for i in range(psi.shape[0]):
+            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g))
+            p = psi[i]
+            mag[i] += c * (np.abs(1.0 - p) * np.abs(k_in @ p) + np.abs(p) * np.abs(k_out @ (1.0 - p)))
+    return 32.0 * np.finfo(np.float64).eps * float(np.max(mag))
 
 
 # ---------------------------------------------------------------- conservation sums and luminosity

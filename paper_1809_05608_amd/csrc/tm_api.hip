@@ -311,6 +311,7 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
         o.res = c->res;
         o.res0 = c->res0;
         o.set_res0 = it == 0;
+        o.skip_inactive = it > 0;
         o.active = c->active;
         o.iters = c->iters;
         o.max_iter = max_iter;
@@ -383,6 +384,16 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
                                             c->stream),
                          "vjp kernel"));
     return TM_OK;
+}
+
+tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, double* seed) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
+    if (!seed) return set_err(c, TM_ERR_INVALID_ARG, "seed is required");
+    TM_TRY(ensure_small(c));
+    const tmk::Shape sh = shape_of(c->p);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    return hip_check(c, tmk::launch_lum_seed(sh, in->r_edge, c->consts, seed, c->stream), "seed kernel");
 }
 
 }  // extern "C"

@@ -59,6 +59,7 @@ struct alignas(16) SysLds {
     T bc[FS];          // broadcast of a zone's psi row (NES) or of x_{i+1} (back substitution)
     T dd[FS];          // NES neighbour factors exp(-(eps_{j+1} - eps_j)/T)
     T fix[NT][FS];     // row-ownership fix-up and transpose staging
+    int sidx[NT];      // slot of the in-place elimination that holds column k of C
 };
 
 template <typename T, int NT, bool TRANS>
@@ -67,6 +68,10 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     constexpr int SPW = 64 / SL;
     constexpr int SPB = (kBlock / 64) * SPW;
     __shared__ SysLds<T, NT> lds_all[SPB];
+    constexpr int PS = NT + 2;                      // row stride of the staged NES shape matrix
+    __shared__ T s_P[NT * PS];
+    for (int j = threadIdx.x; j < NT * NT; j += kBlock) s_P[(j / NT) * PS + (j % NT)] = (T)A.cs->P[j / NT][j % NT];
+    __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / SL, k = lane % SL;
@@ -100,10 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     T* wsY = reinterpret_cast<T*>(A.wsY) + (size_t)sbc * I * NT;
     const bool store = live && real;
 
-    // row k of the NES kernel shape (zone independent)
-    T Prow[NT];
-#pragma unroll
-    for (int kp = 0; kp < NT; ++kp) Prow[kp] = (T)A.cs->P[k < kMaxN ? k : 0][kp];
+    const T* Prow = s_P + kr * PS;                  // row k of the NES shape (zero outside N x N)
     const double de_k = A.cs->de[k < kMaxN ? k : 0];
 
     // ---------------------------------------------------------------- forward sweep
@@ -151,10 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
         if (emabs) diag += c * sig_c;
 
-        // ---- row k of the dense block A_i (before the Schur update)
-        T row[NT];
+        // ---- row k of Ahat_i = A_i - diag(bm_i) C_{i-1} (A^T for the transposed solve)
+        //      NES part of A: -c dt [(1 - psi_k) K^in_{kk'} + psi_k K^out_{kk'}] for every k',
+        //      diagonal: 1 + transport + c dt (eta + kappa_a) + c dt sum_k' [K^in psi + K^out (1 - psi)]
+        T row[NT];                                     // assembled row (only kept for the transpose)
+        T* acc = TRANS ? row : a;
+        {
+            const T s0 = TRANS ? (T)0 : (real ? (T)bm : (T)0);
 #pragma unroll
-        for (int kp = 0; kp < NT; ++kp) row[kp] = (T)0;
+            for (int kp = 0; kp < NT; ++kp) acc[kp] = -s0 * a[kp];
+        }
         if (nes) {
             const double amp = az[i];
             const double Tz = tz[i];
@@ -164,6 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             }
             wave_sync();
             const T pk = (T)psi_c;
+            const T ca = (T)(-c * amp);
+            const T cap = ca * pk, cam = ca * ((T)1 - pk);
             // out factor: exp(-(eps_k' - eps_k)/T) for k' > k, 1 otherwise (ascending product)
             T er = (T)1, so = (T)0, si = (T)0;
 #pragma unroll
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 if (kp > 0) er = (kp > k) ? er * L.dd[kp - 1] : (T)1;
                 const T po = Prow[kp] * er;
                 so = fma(po, (T)1 - L.bc[kp], so);
-                row[kp] = pk * po;                        // psi_k K^out_{kk'} / amp
+                acc[kp] = fma(cap, po, acc[kp]);           // - c dt psi_k K^out_{kk'}
             }
             // in factor: exp(-(eps_k - eps_k')/T) for k' < k, 1 otherwise (descending product)
             T el = (T)1;
@@ -180,30 +190,24 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 el = (kp < k) ? el * L.dd[kp] : (T)1;
                 const T pi = Prow[kp] * el;
                 si = fma(pi, L.bc[kp], si);
-                row[kp] = fma((T)1 - pk, pi, row[kp]);   // + (1 - psi_k) K^in_{kk'} / amp
+                acc[kp] = fma(cam, pi, acc[kp]);           // - c dt (1 - psi_k) K^in_{kk'}
             }
-            const T ca = (T)(-c * amp);
-#pragma unroll
-            for (int kp = 0; kp < NT; ++kp) row[kp] = (kp < N) ? ca * row[kp] : (T)0;
             diag += c * amp * (double)(si + so);
         }
         if (real) {
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) row[kp] += (kp == k) ? (T)diag : (T)0;
+            for (int kp = 0; kp < NT; ++kp) acc[kp] += (kp == k) ? (T)diag : (T)0;
         } else {
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) row[kp] = (kp == k) ? (T)1 : (T)0;   // padded identity row
+            for (int kp = 0; kp < NT; ++kp) acc[kp] = (kp == k) ? (T)1 : (T)0;   // padded identity row
             bm = bp = bm_next = 0.0;
         }
 
-        // ---- Schur complement and right-hand side
+        // ---- right-hand side (and, for the transpose, the transposed block plus its Schur update)
         T g = real ? (T)(A.rhs_sign * rhs[(size_t)i * N + kk]) : (T)0;
         T bcoef;
         if constexpr (!TRANS) {
-            const T s = (T)bm;
-#pragma unroll
-            for (int kp = 0; kp < NT; ++kp) a[kp] = fma(-s, a[kp], row[kp]);
-            g = fma(-s, ycar, g);
+            g = fma(-(T)bm, ycar, g);
             bcoef = (T)bp;
         } else {
             if (is_row) {
@@ -223,7 +227,6 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         bool used = !is_row;
         T mypiv = (T)1;
         int mycol = 0;
-        int pstep[NT];
 #pragma unroll
         for (int cc = 0; cc < NT; ++cc) {
             const T ac = a[cc];
@@ -254,20 +257,21 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 mypiv = piv;
                 mycol = cc;
             }
-            pstep[cc] = p;
             wave_sync();
         }
 
-        // ---- restore row ownership: lane holding unknown mycol writes its scaled row
+        // ---- restore row ownership: the lane holding unknown mycol writes its scaled row in slot
+        //      order; slot sidx[m] (the step at which lane m was the pivot) holds column m of C
         if (is_row) {
             const T ip = (T)1 / mypiv;
 #pragma unroll
-            for (int cc = 0; cc < NT; ++cc) L.fix[mycol][pstep[cc]] = a[cc] * ip;
+            for (int cc = 0; cc < NT; ++cc) L.fix[mycol][cc] = a[cc] * ip;
             L.fix[mycol][NT] = g * ip;
+            L.sidx[k] = mycol;
         }
         wave_sync();
 #pragma unroll
-        for (int m = 0; m < NT; ++m) a[m] = is_row ? L.fix[kr][m] : (T)0;
+        for (int m = 0; m < NT; ++m) a[m] = is_row ? L.fix[kr][L.sidx[m]] : (T)0;
         ycar = is_row ? L.fix[kr][NT] : (T)0;
         wave_sync();
 

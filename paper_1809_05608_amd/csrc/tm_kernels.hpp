@@ -18,6 +18,7 @@ struct ResidualOut {
     double* lum;
     int set_res0;
     int stats;
+    int skip_inactive;  // systems with active == 0 are left untouched (Newton iterations after the first)
     int max_iter;
     double rtol;
 };
@@ -54,6 +55,8 @@ hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, hipStre
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,
                       hipStream_t st);
+
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, double* seed, hipStream_t st);
 
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
 

@@ -147,105 +147,137 @@ __device__ __forceinline__ int block_or(int v, double* sh) {
 
 // ---------------------------------------------------------------- residual / statistics
 
+// Mapping: one block per system.  The 256 threads cover ZB = 256/NT consecutive zones x NT
+// groups (thread = cell, so every global access is coalesced) and step through the system
+// in chunks of ZB zones.  Each chunk's psi rows and NES neighbour factors are staged in LDS
+// for the O(N) NES sums of a cell; the NES shape matrix is staged once per block.
+// Besides max|G| the kernel computes the rounding level of G (32 ulp of the largest sum of
+// term magnitudes in the system), below which the Newton stopping rule does not ask for
+// further progress.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const Consts* __restrict__ cs,
                                                      const double* __restrict__ psi_n,
                                                      const double* __restrict__ psi, double* __restrict__ G_out,
                                                      double g_sign, ResidualOut out) {
+    constexpr int ZB = kBlock / NT;
+    constexpr int PS = NT + 1;                  // padded LDS row stride (conflict-free column reads)
+    __shared__ double s_P[NT * PS];
+    __shared__ double s_psi[ZB][PS];
+    __shared__ double s_d[ZB][PS];
     __shared__ double red[kBlock / 64];
     const long long sys = blockIdx.x;
+    if (out.skip_inactive && out.active && out.active[sys] == 0) return;   // converged before: unchanged
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
     const double* re = f.r_edge + (size_t)ray * (I + 1);
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+    const int t = threadIdx.x, zl = t / NT, k = t - zl * NT;
+    const bool tile = zl < ZB;
+    const bool lane_ok = tile && k < N;
 
-    double gmax = 0.0;
+    if (nes)
+        for (int j = t; j < NT * NT; j += kBlock) s_P[(j / NT) * PS + (j % NT)] = cs->P[j / NT][j % NT];
+
+    double gmax = 0.0, gscale = 0.0;
     int bad = 0;
     double s_n = 0.0, s_nold = 0.0, s_e = 0.0, s_q = 0.0, s_nes = 0.0, s_b = 0.0;
+    const double Wk = lane_ok ? cs->W[k] : 0.0;
+    const double epsk = lane_ok ? cs->eps[k] : 0.0;
+    const double dek = (lane_ok && k + 1 < N) ? cs->de[k] : 0.0;
 
-    for (int i = threadIdx.x; i < I; i += kBlock) {
-        const size_t cb = ((size_t)sys * I + i) * N;
-        const ZoneGeom g = zone_geom(re, i, I);
-        double p[NT], G[NT], Hhi[NT];
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            p[k] = 0.0;
-            G[k] = 0.0;
-            Hhi[k] = 0.0;
-            if (k < N) {
-                p[k] = psi[cb + k];
-                G[k] = p[k] - psi_n[cb + k];
-            }
+    for (int z0 = 0; z0 < I; z0 += ZB) {
+        const int i = z0 + zl;
+        const bool ok = lane_ok && i < I;
+        const size_t cb = ((size_t)sys * I + (ok ? i : 0)) * N + (ok ? k : 0);
+        const double p = ok ? psi[cb] : 0.0;
+        __syncthreads();                                    // previous chunk done with the LDS rows
+        if (tile) {
+            s_psi[zl][k] = ok ? p : 0.0;
+            s_d[zl][k] = (nes && ok && k + 1 < N) ? exp(-dek / f.temp[(size_t)ray * I + i]) : 0.0;
         }
+        __syncthreads();
+        if (!ok) continue;
+
+        const double pn = psi_n[cb];
+        double G = p - pn;
+        double scale = fabs(p) + fabs(pn);
+        const double rlo = re[i], rhi = re[i + 1];
+        const double V = shell_volume(rlo, rhi);
+        double Hh = 0.0;
         if (diff) {
-#pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                if (k >= N) break;
-                const double lam = inv_mfp(f, cb + k);
-                double Hlo = 0.0, Hh = 0.0;
-                if (i > 0) {
-                    const size_t cm = cb - N + k;
-                    const double lam_e = sqrt(lam * inv_mfp(f, cm));
-                    Hlo = edge_flux(psi[cm], p[k], lam_e, g.D_lo, sh.psi_floor, sh.limiter).H;
-                }
-                if (i + 1 < I) {
-                    const size_t cp = cb + N + k;
-                    const double lam_e = sqrt(lam * inv_mfp(f, cp));
-                    Hh = edge_flux(p[k], psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter).H;
-                } else if (sh.outer_bc == 1) {
-                    Hh = p[k];                                 // free streaming, eq. a22 limit
-                }
-                Hhi[k] = Hh;
-                G[k] += c * (g.A_hi * Hh - g.A_lo * Hlo) / g.V;
+            const double A_lo = rlo * rlo, A_hi = rhi * rhi, rc = 0.5 * (rlo + rhi);
+            const double lam = inv_mfp(f, cb);
+            double Hlo = 0.0;
+            if (i > 0) {
+                const size_t cm = cb - N;
+                const double D_lo = rc - 0.5 * (re[i - 1] + rlo);
+                Hlo = edge_flux(psi[cm], p, sqrt(lam * inv_mfp(f, cm)), D_lo, sh.psi_floor, sh.limiter).H;
             }
+            if (i + 1 < I) {
+                const size_t cp = cb + N;
+                const double D_hi = 0.5 * (rhi + re[i + 2]) - rc;
+                Hh = edge_flux(p, psi[cp], sqrt(lam * inv_mfp(f, cp)), D_hi, sh.psi_floor, sh.limiter).H;
+            } else if (sh.outer_bc == 1) {
+                Hh = p;                                     // free streaming, eq. a22 limit
+            }
+            G += c * (A_hi * Hh - A_lo * Hlo) / V;
+            scale += c * (fabs(A_hi * Hh) + fabs(A_lo * Hlo)) / V;
         }
+        double ka = 0.0, et = 0.0;
         if (emabs) {
-#pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                if (k >= N) break;
-                G[k] += c * (f.kappa_a[cb + k] * p[k] - f.eta[cb + k] * (1.0 - p[k]));
-            }
+            ka = f.kappa_a[cb];
+            et = f.eta[cb];
+            G += c * (ka * p - et * (1.0 - p));
+            scale += c * (fabs(ka * p) + fabs(et * (1.0 - p)));
         }
-        double S[NT];
-#pragma unroll
-        for (int k = 0; k < NT; ++k) S[k] = 0.0;
+        double S = 0.0;
         if (nes) {
             const double amp = f.nes_amp[(size_t)sys * I + i];
-            const double T = f.temp[(size_t)ray * I + i];
-            double si[NT], so[NT];
-            nes_zone<NT>(cs, N, T, p, si, so);
+            double sin_ = 0.0, sout = 0.0, e = 1.0;
+            // k' > k: the out kernel carries exp(-(eps_k' - eps_k)/T) = prod_{j=k}^{k'-1} d_j
 #pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                if (k >= N) break;
-                S[k] = amp * ((1.0 - p[k]) * si[k] - p[k] * so[k]);
-                G[k] -= c * S[k];
+            for (int kp = 1; kp < NT; ++kp) {
+                if (kp >= N) break;
+                if (kp > k) {
+                    const double Pk = s_P[k * PS + kp], pp = s_psi[zl][kp];
+                    e *= s_d[zl][kp - 1];
+                    sout = fma(Pk * e, 1.0 - pp, sout);
+                    sin_ = fma(Pk, pp, sin_);
+                }
             }
-        }
+            // k' < k: the in kernel carries exp(-(eps_k - eps_k')/T) = prod_{j=k'}^{k-1} d_j
+            e = 1.0;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (k >= N) break;
-            const double a = fabs(G[k]);
-            bad |= !isfinite(G[k]);
-            gmax = fmax(gmax, a);
-            if (G_out) G_out[cb + k] = g_sign * G[k];
+            for (int kp = NT - 2; kp >= 0; --kp) {
+                if (kp < k) {
+                    const double Pk = s_P[k * PS + kp], pp = s_psi[zl][kp];
+                    e *= s_d[zl][kp];
+                    sin_ = fma(Pk * e, pp, sin_);
+                    sout = fma(Pk, 1.0 - pp, sout);
+                }
+            }
+            S = amp * ((1.0 - p) * sin_ - p * sout);
+            G -= c * S;
+            scale += c * amp * (fabs(1.0 - p) * fabs(sin_) + fabs(p) * fabs(sout));
         }
+        bad |= !isfinite(G);
+        gmax = fmax(gmax, fabs(G));
+        gscale = fmax(gscale, scale);
+        if (G_out) G_out[cb] = g_sign * G;
         if (out.stats) {
-#pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                if (k >= N) break;
-                const double vw = g.V * cs->W[k];
-                s_n = fma(vw, p[k], s_n);
-                s_nold = fma(vw, psi_n[cb + k], s_nold);
-                s_e = fma(vw * cs->eps[k], p[k], s_e);
-                if (emabs) s_q = fma(c * vw, f.eta[cb + k] * (1.0 - p[k]) - f.kappa_a[cb + k] * p[k], s_q);
-                if (nes) s_nes = fma(c * vw, S[k], s_nes);
-                if (i == I - 1 && diff) s_b = fma(cs->W[k], Hhi[k], s_b);
-            }
+            const double vw = V * Wk;
+            s_n = fma(vw, p, s_n);
+            s_nold = fma(vw, pn, s_nold);
+            s_e = fma(vw * epsk, p, s_e);
+            if (emabs) s_q = fma(c * vw, et * (1.0 - p) - ka * p, s_q);
+            if (nes) s_nes = fma(c * vw, S, s_nes);
+            if (i == I - 1 && diff) s_b = fma(Wk, Hh, s_b);
         }
     }
 
     const double res = block_max(gmax, red);
+    const double floor_g = 32.0 * 2.220446049250313e-16 * block_max(gscale, red);
     bad = block_or(bad, red);
     if (out.stats) {
         s_n = block_sum(s_n, red);
@@ -260,14 +292,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         double r0 = res;
         if (out.set_res0 && out.res0) out.res0[sys] = bad ? __builtin_nan("") : res;
         else if (out.res0) r0 = out.res0[sys];
-        const bool stop = !bad && res <= out.rtol * r0;          // Newton stopping rule
+        // Newton stopping rule: max|G| <= max(rtol * max|G_0|, rounding level of G); rtol = 0 means
+        // a fixed number of updates
+        const bool stop = !bad && out.rtol > 0.0 && res <= fmax(out.rtol * r0, floor_g);
         if (out.active) {
             const int it = out.iters ? out.iters[sys] : 0;
-            out.active[sys] = (!stop && !bad && it < out.max_iter) ? 1 : 0;
+            out.active[sys] = (!stop && !bad && it < out.max_iter && res > 0.0) ? 1 : 0;
         }
         if (out.flags) {
             int fl = out.flags[sys] & 4;   // keep zero-pivot bit from the factorisation
-            if (out.rtol > 0.0 && !stop) fl |= 1;                  // rtol = 0: fixed count, no target
+            if (out.rtol > 0.0 && !stop) fl |= 1;
             if (bad) fl |= 2;
             out.flags[sys] = fl;
         }
@@ -422,6 +456,31 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
             g_amp[(size_t)sys * I + i] = ga;
         }
     }
+}
+
+// ---------------------------------------------------------------- luminosity seed
+
+// dL_N/dpsi for L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k} with free streaming H = psi of the
+// last zone: c R_{I+1/2}^2 W_k in the outermost zone, zero elsewhere (and zero everywhere
+// when there is no outgoing flux).
+__global__ __launch_bounds__(kBlock) void k_lum_seed(Shape sh, const double* __restrict__ r_edge,
+                                                     const Consts* __restrict__ cs, double* __restrict__ seed) {
+    const long long sys = blockIdx.x;
+    const int I = sh.I, N = sh.N;
+    const int ray = (int)(sys % sh.R);
+    const bool flux = (sh.terms & kDiffusion) && sh.outer_bc == 1;
+    const double ro = r_edge[(size_t)ray * (I + 1) + I];
+    const size_t n = (size_t)I * N;
+    for (size_t j = threadIdx.x; j < n; j += kBlock) {
+        const int i = (int)(j / N), k = (int)(j % N);
+        seed[(size_t)sys * n + j] = (flux && i == I - 1) ? kCLight * ro * ro * cs->W[k] : 0.0;
+    }
+}
+
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, double* seed, hipStream_t st) {
+    const long long nsys = (long long)sh.S * sh.R;
+    hipLaunchKernelGGL(k_lum_seed, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, r_edge, cs, seed);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- active-system count

@@ -26,7 +26,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_ZERO_PIVOT = 1, 2, 4
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
-            "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_status_string", "tm_last_error"]
+            "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_status_string",
+            "tm_last_error"]
 
 
 class TMError(RuntimeError):
@@ -73,12 +74,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_factor_solve.argtypes = [V, P(Inputs), V, V, V, I32]
     lib.tm_newton_step.argtypes = [V, P(Inputs), V, V, I32, D, P(Stats)]
     lib.tm_adjoint_step.argtypes = [V, P(Inputs), V, V, V, V, V, V, V, V]
+    lib.tm_luminosity_seed.argtypes = [V, P(Inputs), V]
     lib.tm_status_string.argtypes = [ctypes.c_int]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = [V]
     lib.tm_last_error.restype = ctypes.c_char_p
     for name in ("tm_create", "tm_destroy", "tm_set_workspace", "tm_assemble", "tm_factor_solve",
-                 "tm_newton_step", "tm_adjoint_step"):
+                 "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -240,6 +242,12 @@ class Context:
                                              _ptr(mu), _ptr(g_kappa_a), _ptr(g_eta), _ptr(g_kappa_s),
                                              _ptr(g_nes_amp)))
 
+    def luminosity_seed(self, f: DeviceFields, seed):
+        """dL_N/dpsi of the outer-boundary number luminosity into `seed` (cell array)."""
+        self._cell(seed, "seed")
+        inp = self._inputs(f)
+        self._check(self.lib.tm_luminosity_seed(self._h, ctypes.byref(inp), _ptr(seed)))
+
 
 # ---------------------------------------------------------------------- autograd
 
@@ -273,15 +281,3 @@ class TransportStep(torch.autograd.Function):
         gks = torch.empty_like(psi) if need[2] else None
         ctx.tmctx.adjoint_step(f, psi_n, psi, grad.contiguous(), mu, gka, get, gks, None)
         return gka, get, gks, (mu if need[3] else None), None, None, None, None
-
-
-def luminosity_weights(w_or_fields, device=None) -> torch.Tensor:
-    """Seed weights c A_{I+1/2} W_k of the outer-boundary number luminosity, [R][N] (float64).
-
-    Grid bookkeeping for the objective only (the transport arithmetic runs in libtm).
-    """
-    r_edge, e_edge = w_or_fields.r_edge, w_or_fields.e_edge
-    lo, hi = e_edge[:-1], e_edge[1:]
-    W = (hi - lo) * (hi * hi + hi * lo + lo * lo) / 3.0
-    A = r_edge[:, -1] ** 2
-    return 2.99792458e10 * A[:, None] * W[None, :]

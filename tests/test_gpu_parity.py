@@ -201,7 +201,10 @@ def test_adjoint_matches_oracle():
     seed = np.zeros_like(ref)
     for r in range(w.R):
         seed[0, r] = oracle.luminosity_seed(syss[0][r], ref[0, r].shape)
-    seed_d = torch.as_tensor(seed, device="cuda")
+    seed_d = torch.empty_like(psi)
+    ctx.luminosity_seed(f, seed_d)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(seed_d.cpu().numpy(), seed, rtol=1e-14, atol=0)
     mu = torch.empty_like(psi)
     g = {n: torch.empty_like(psi) for n in ("kappa_a", "eta", "kappa_s")}
     gamp = torch.empty(w.S, w.R, w.I, dtype=torch.float64, device="cuda")
@@ -215,8 +218,12 @@ def test_adjoint_matches_oracle():
         for n in g:
             gs = np.max(np.abs(go[n]))
             np.testing.assert_allclose(g[n][0, r].cpu().numpy(), go[n], rtol=1e-9, atol=1e-11 * gs)
-        np.testing.assert_allclose(gamp[0, r].cpu().numpy(), go["nes_amp"], rtol=1e-9,
-                                   atol=1e-11 * np.max(np.abs(go["nes_amp"])))
+        # g_amp_i = c sum_k mu_ik S_ik nearly cancels where mu_k ~ W_k (number conservation makes
+        # sum_k W_k S_k = 0), so its rounding floor scales with sum_k |mu_ik S_ik|, not with |g|
+        S1 = oracle.transport.nes_source(syss[0][r], ref[0, r], unit_amplitude=True)
+        floor = w.c_dt * np.sum(np.abs(mo * S1), axis=1)
+        err = np.abs(gamp[0, r].cpu().numpy() - go["nes_amp"])
+        assert np.all(err <= 1e-12 * floor + 1e-9 * np.abs(go["nes_amp"])), (err, floor)
 
 
 def test_transport_step_autograd_matches_oracle_gradient():
@@ -228,8 +235,9 @@ def test_transport_step_autograd_matches_oracle_gradient():
     et = wd.eta.clone().requires_grad_(True)
     pn = wd.psi_n.clone().requires_grad_(True)
     psi = tm.TransportStep.apply(ka, et, wd.kappa_s, pn, ctx, f, 40, 1e-14)
-    wl = tm.luminosity_weights(wd)                             # [R][N]
-    L = (psi[:, :, -1, :] * wl[None]).sum()
+    seed = torch.empty_like(psi)
+    ctx.luminosity_seed(f, seed)                               # dL/dpsi, outer zone only
+    L = (psi * seed).sum()
     L.backward()
     wn = w.numpy()
     syss = oracle.systems_from_workload(wn)

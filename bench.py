@@ -156,8 +156,13 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short pass for rocprofv3: one mixed step, one launch of each timed kernel, "
+                         "and a plain 1 GiB device copy that calibrates the HBM byte counters")
     a = ap.parse_args(argv)
+    if a.profile_pass:
+        a.steps, a.warmup, a.kernel_reps, a.no_fp64, a.no_cpu = 1, 0, 1, True, True
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested); the transport systems of a "
               "multi-GPU run would be sharded by ray with no exchange inside a step", file=sys.stderr)
@@ -176,6 +181,15 @@ def main(argv=None):
     torch.cuda.synchronize()
     cells = w.n_cells
     log(f"workload {w.name}: {w.S}x{w.R}x{w.I}x{w.N} = {cells} cells")
+
+    if a.profile_pass:
+        # calibration: a plain copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB device-to-device copy done")
 
     # ---------------- mixed-precision leg (headline)
     log("mixed-precision Newton")

@@ -350,14 +350,20 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
     hist = []
     res0 = None
     iters = 0
+    prev = np.inf
     for _ in range(max_iter):
         G = residual(sys, psi_n, psi)
         r = float(np.max(np.abs(G)))
         hist.append(r)
         if res0 is None:
             res0 = r
-        if r == 0.0 or (rtol > 0.0 and r <= max(rtol * res0, residual_rounding_level(sys, psi_n, psi))):
+        if r == 0.0:
             break
+        if rtol > 0.0:
+            target = max(rtol * res0, residual_rounding_level(sys, psi_n, psi))
+            if r <= target or (r <= 1e3 * target and r > 0.5 * prev):
+                break          # reached, or stalled: the update is below the resolution of psi
+        prev = r
         blocks, bm, bp = jacobian_blocks(sys, psi)
         psi = psi + block_thomas_solve(blocks, bm, bp, -G)
         iters += 1
@@ -371,25 +377,32 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
 
 
 def residual_rounding_level(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> float:
-    """32 ulp of the largest per-cell sum of the magnitudes of the terms of G.
+    """32 ulp of the largest per-cell sum of the magnitudes of G's terms plus |psi| |dG/dpsi|.
 
-    G is a sum of terms that nearly cancel near the solution; below this level the
-    computed residual is rounding, so the stopping rule asks for no progress beyond it.
+    G is a sum of terms that nearly cancel near the solution, and a change of psi by one
+    ulp moves G by about |dG/dpsi| ulp(psi); below this level the computed residual is
+    rounding, so the stopping rule asks for no progress beyond it.
     """
     _, V, A, _ = geometry(sys.r_edge)
     c = sys.c_dt
     mag = np.abs(psi) + np.abs(psi_n)
+    jd = np.ones_like(psi)              # bound of |dG_ik/dpsi_ik|
     if sys.terms & TERM_DIFFUSION:
-        H = _edge_fluxes(sys, psi)[0]
+        H, dHu, dHv, _, _ = _edge_fluxes(sys, psi)
         mag = mag + c * (np.abs(A[1:, None] * H[1:]) + np.abs(A[:-1, None] * H[:-1])) / V[:, None]
+        jd = jd + c * (A[1:, None] * np.abs(dHu[1:]) + A[:-1, None] * np.abs(dHv[:-1])) / V[:, None]
     if sys.terms & TERM_EMABS:
         mag = mag + c * (np.abs(sys.kappa_a * psi) + np.abs(sys.eta * (1.0 - psi)))
+        jd = jd + c * (sys.kappa_a + sys.eta)
     if sys.terms & TERM_NES:
         eps, W = group_energies(sys.e_edge)
         for i in range(psi.shape[0]):
             k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g))
             p = psi[i]
-            mag[i] += c * (np.abs(1.0 - p) * np.abs(k_in @ p) + np.abs(p) * np.abs(k_out @ (1.0 - p)))
+            si, so = k_in @ p, k_out @ (1.0 - p)
+            mag[i] += c * (np.abs(1.0 - p) * np.abs(si) + np.abs(p) * np.abs(so))
+            jd[i] += c * (np.abs(si) + np.abs(so))
+    mag = mag + np.abs(psi) * jd
     return 32.0 * np.finfo(np.float64).eps * float(np.max(mag))
 
 

@@ -205,24 +205,31 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         const double rlo = re[i], rhi = re[i + 1];
         const double V = shell_volume(rlo, rhi);
         double Hh = 0.0;
+        double jd = 1.0;                                    // |dG_ik/dpsi_ik| bound, for the rounding level
         if (diff) {
             const double A_lo = rlo * rlo, A_hi = rhi * rhi, rc = 0.5 * (rlo + rhi);
             const double lam = inv_mfp(f, cb);
-            double Hlo = 0.0;
+            double Hlo = 0.0, dlo = 0.0, dhi = 0.0;
             if (i > 0) {
                 const size_t cm = cb - N;
                 const double D_lo = rc - 0.5 * (re[i - 1] + rlo);
-                Hlo = edge_flux(psi[cm], p, sqrt(lam * inv_mfp(f, cm)), D_lo, sh.psi_floor, sh.limiter).H;
+                const EdgeFlux e = edge_flux(psi[cm], p, sqrt(lam * inv_mfp(f, cm)), D_lo, sh.psi_floor, sh.limiter);
+                Hlo = e.H;
+                dlo = e.dHv;
             }
             if (i + 1 < I) {
                 const size_t cp = cb + N;
                 const double D_hi = 0.5 * (rhi + re[i + 2]) - rc;
-                Hh = edge_flux(p, psi[cp], sqrt(lam * inv_mfp(f, cp)), D_hi, sh.psi_floor, sh.limiter).H;
+                const EdgeFlux e = edge_flux(p, psi[cp], sqrt(lam * inv_mfp(f, cp)), D_hi, sh.psi_floor, sh.limiter);
+                Hh = e.H;
+                dhi = e.dHu;
             } else if (sh.outer_bc == 1) {
                 Hh = p;                                     // free streaming, eq. a22 limit
+                dhi = 1.0;
             }
             G += c * (A_hi * Hh - A_lo * Hlo) / V;
             scale += c * (fabs(A_hi * Hh) + fabs(A_lo * Hlo)) / V;
+            jd += c * (A_hi * fabs(dhi) + A_lo * fabs(dlo)) / V;
         }
         double ka = 0.0, et = 0.0;
         if (emabs) {
@@ -230,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
             et = f.eta[cb];
             G += c * (ka * p - et * (1.0 - p));
             scale += c * (fabs(ka * p) + fabs(et * (1.0 - p)));
+            jd += c * (ka + et);
         }
         double S = 0.0;
         if (nes) {
@@ -260,7 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
             S = amp * ((1.0 - p) * sin_ - p * sout);
             G -= c * S;
             scale += c * amp * (fabs(1.0 - p) * fabs(sin_) + fabs(p) * fabs(sout));
+            jd += c * amp * (fabs(sin_) + fabs(sout));
         }
+        scale += fabs(p) * jd;                              // G changes by jd * ulp(psi) per ulp of psi
         bad |= !isfinite(G);
         gmax = fmax(gmax, fabs(G));
         gscale = fmax(gscale, scale);
@@ -288,20 +298,25 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         s_b = block_sum(s_b, red);
     }
     if (threadIdx.x == 0) {
+        const double prev = out.set_res0 ? __builtin_inf() : out.res[sys];
         out.res[sys] = bad ? __builtin_nan("") : res;
         double r0 = res;
         if (out.set_res0 && out.res0) out.res0[sys] = bad ? __builtin_nan("") : res;
         else if (out.res0) r0 = out.res0[sys];
-        // Newton stopping rule: max|G| <= max(rtol * max|G_0|, rounding level of G); rtol = 0 means
-        // a fixed number of updates
-        const bool stop = !bad && out.rtol > 0.0 && res <= fmax(out.rtol * r0, floor_g);
+        // Newton stopping rule: max|G| <= max(rtol * max|G_0|, rounding level of G), or no halving
+        // of max|G| within 1000x of that target (the update is below the resolution of psi);
+        // rtol = 0 means a fixed number of updates
+        const double target = fmax(out.rtol * r0, floor_g);
+        const bool reached = !bad && out.rtol > 0.0 && res <= target;
+        const bool stalled = !bad && out.rtol > 0.0 && res <= 1e3 * target && res > 0.5 * prev;
+        const bool stop = reached || stalled;
         if (out.active) {
             const int it = out.iters ? out.iters[sys] : 0;
             out.active[sys] = (!stop && !bad && it < out.max_iter && res > 0.0) ? 1 : 0;
         }
         if (out.flags) {
             int fl = out.flags[sys] & 4;   // keep zero-pivot bit from the factorisation
-            if (out.rtol > 0.0 && !stop) fl |= 1;
+            if (out.rtol > 0.0 && !reached) fl |= 1;
             if (bad) fl |= 2;
             out.flags[sys] = fl;
         }

@@ -178,7 +178,9 @@ def test_mixed_precision_refines_to_fp64_answer():
     assert st == 0, tm.STATUS_NAMES[st]
     ref, info = oracle_newton(w, 30, 1e-12)
     assert rel_err(psi, ref) < MIXED_BAR
-    assert np.all(stats["res_inf"] <= 1e-12 * stats["res0_inf"])
+    # every system reached max(1e-12 * res0, rounding level of G)
+    assert not np.any(stats["flags"] & tm.FLAG_NOT_CONVERGED)
+    assert np.all(stats["res_inf"] <= 1e-10 * stats["res0_inf"])
 
 
 # ------------------------------------------------------------------ adjoint

@@ -90,6 +90,9 @@ typedef enum {
 #define TM_FLAG_NOT_CONVERGED 1
 #define TM_FLAG_NONFINITE     2
 #define TM_FLAG_ZERO_PIVOT    4
+#define TM_FLAG_PIVOT_FALLBACK 8  /* informational: re-factored with partial pivoting after the
+                                     diagonal-pivot growth guard tripped (|multiplier| > 16,
+                                     zero or non-finite pivot)                               */
 
 #define TM_MAX_GROUPS 32
 
@@ -157,8 +160,12 @@ tm_status tm_assemble(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
                       const double *psi, double *residual, double *blocks);
 
 /* Solve J(psi) x = rhs (transpose = 0) or J(psi)^T x = rhs (transpose != 0) for
- * every system by block-Thomas elimination (eq. a62ae) with partial pivoting inside
- * each dense block.  rhs and x are cell arrays and may alias.  In TM_PREC_MIXED the
+ * every system by block-Thomas elimination (eq. a62ae).  Each dense block is eliminated
+ * with diagonal pivots (the blocks of this method are column diagonally dominant) under a
+ * growth guard; a system that trips it is re-factored with partial pivoting
+ * (TM_FLAG_PIVOT_FALLBACK).  The environment variable TM_PIVOT=always|never read at
+ * tm_create forces partial pivoting or disables the fallback; TM_GROWTH_LIMIT sets
+ * the guard (default 16).  rhs and x are cell arrays and may alias.  In TM_PREC_MIXED the
  * factorisation and solve run in float32 (x is the float32 solution widened).      */
 tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
                           const double *rhs, double *x, int32_t transpose);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -31,6 +32,13 @@ struct tm_ctx {
     int* count = nullptr;       // [1]
     double* gbuf = nullptr;     // [cells] residual for the Newton right-hand side
     int* h_count = nullptr;     // pinned host
+    int* guard = nullptr;       // [nsys] growth guard of the last diagonal-pivot launch
+    int* redo = nullptr;        // [nsys] systems re-factored with partial pivoting
+    // pivoting policy: 0 diagonal pivots with guarded fallback to partial pivoting (default),
+    // 1 always partial pivoting, 2 diagonal pivots only (guard trips become failures)
+    int pivot_policy = 0;
+    double growth_limit = 16.0;
+    long long pivot_fallbacks = 0;   // systems re-factored with partial pivoting since creation
 };
 
 namespace {
@@ -121,6 +129,8 @@ tm_status ensure_small(tm_ctx* c) {
     TM_TRY(hip_check(c, hipMalloc((void**)&c->flags, ns * sizeof(int)), "hipMalloc flags"));
     TM_TRY(hip_check(c, hipMalloc((void**)&c->count, sizeof(int)), "hipMalloc count"));
     TM_TRY(hip_check(c, hipHostMalloc((void**)&c->h_count, sizeof(int)), "hipHostMalloc"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->guard, ns * sizeof(int)), "hipMalloc guard"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->redo, ns * sizeof(int)), "hipMalloc redo"));
     return TM_OK;
 }
 
@@ -172,13 +182,35 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     a.active = active;
     a.flags = c->flags;
     a.iters = psi_out ? c->iters : nullptr;
+    a.guard = c->guard;
+    a.growth_limit = c->growth_limit;
     a.wsC = c->ws;
     a.wsY = (char*)c->ws + (size_t)batch * c->p.n_zones * NT * NT * es;
     const long long ns = n_systems(c->p);
+    const bool pivot_first = c->pivot_policy == 1;
+    if (!pivot_first)
+        TM_TRY(hip_check(c, hipMemsetAsync(c->guard, 0, ns * sizeof(int), c->stream), "memset guard"));
     for (long long s0 = 0; s0 < ns; s0 += batch) {
         a.sys0 = s0;
         a.nsys = std::min(batch, ns - s0);
-        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, c->stream), "factor kernel"));
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, pivot_first, c->stream), "factor kernel"));
+    }
+    if (pivot_first) return TM_OK;
+    // systems whose diagonal-pivot elimination tripped the growth guard were left untouched:
+    // re-factor exactly those with partial pivoting
+    TM_TRY(hip_check(c, tmk::launch_mark(c->guard, ns, c->redo, c->count, c->stream), "mark kernel"));
+    TM_TRY(hip_check(c, hipMemcpyAsync(c->h_count, c->count, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                     "copy count"));
+    TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+    const int nredo = *c->h_count;
+    if (nredo == 0) return TM_OK;
+    c->pivot_fallbacks += nredo;
+    if (c->pivot_policy == 2) return set_err(c, TM_ERR_SINGULAR, "diagonal-pivot growth guard tripped");
+    a.active = c->redo;
+    for (long long s0 = 0; s0 < ns; s0 += batch) {
+        a.sys0 = s0;
+        a.nsys = std::min(batch, ns - s0);
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, true, c->stream), "pivoting factor kernel"));
     }
     return TM_OK;
 }
@@ -217,6 +249,12 @@ tm_status tm_create(const tm_problem* p, void* stream, tm_ctx** out) {
     tm_ctx* c = new tm_ctx();
     c->p = *p;
     c->stream = (hipStream_t)stream;
+    // test and tuning knobs: TM_PIVOT = auto | always | never, TM_GROWTH_LIMIT = <double>
+    if (const char* e = std::getenv("TM_PIVOT")) {
+        if (!std::strcmp(e, "always")) c->pivot_policy = 1;
+        else if (!std::strcmp(e, "never")) c->pivot_policy = 2;
+    }
+    if (const char* e = std::getenv("TM_GROWTH_LIMIT")) c->growth_limit = std::atof(e);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return TM_ERR_HIP;
@@ -237,6 +275,8 @@ tm_status tm_destroy(tm_ctx* c) {
         (void)hipFree(c->flags);
         (void)hipFree(c->count);
         (void)hipHostFree(c->h_count);
+        (void)hipFree(c->guard);
+        (void)hipFree(c->redo);
     }
     if (c->gbuf) (void)hipFree(c->gbuf);
     if (c->ws && c->ws_owned) (void)hipFree(c->ws);

@@ -31,6 +31,21 @@ __device__ __forceinline__ uint32_t abs_key_bits(float v) { return __float_as_ui
 __device__ __forceinline__ double texp(double x) { return exp(x); }
 __device__ __forceinline__ float texp(float x) { return __expf(x); }
 
+// Reciprocal from the hardware estimate refined by Newton steps (one for float, two for
+// double), instead of the full IEEE division sequence.  Zero gives a non-finite result.
+__device__ __forceinline__ float rcp_nr(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Max of a 32-bit key over each SL-lane group (SL = 16 or 32) of the wavefront.
 template <int SL>
 __device__ __forceinline__ uint32_t group_max(uint32_t v) {
@@ -62,7 +77,13 @@ struct alignas(16) SysLds {
     int sidx[NT];      // slot of the in-place elimination that holds column k of C
 };
 
-template <typename T, int NT, bool TRANS>
+// PIVOT = false: diagonal pivots with a growth guard.  The blocks of this method are
+// column diagonally dominant (identity plus positive diagonal terms; the NES and transport
+// couplings conserve number, so their V/W-weighted column sums vanish), for which elimination
+// without pivoting is stable.  A system whose multipliers exceed A.growth_limit, or that
+// meets a zero or non-finite pivot, is not updated and is marked in A.guard so that the
+// host can re-factor it with PIVOT = true (partial pivoting).
+template <typename T, int NT, bool TRANS, bool PIVOT>
 __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     constexpr int SL = NT > 16 ? 32 : 16;
     constexpr int SPW = 64 / SL;
@@ -118,8 +139,13 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     double lam_c = real ? 1.0 / (sig_c + ks[kk]) : 1.0;
     double dHu_lo = 0.0, dHv_lo = 0.0, bp_prev = 0.0;
     bool zp = false;
+    T growth = (T)0;                                  // largest |multiplier| (diagonal pivots)
 
     for (int i = 0; i < I; ++i) {
+        // lane index re-materialised per zone: comparisons with it are evaluated where used
+        // instead of being hoisted out of the zone loop as dozens of live lane masks
+        int kz = k;
+        asm volatile("" : "+v"(kz));
         // next zone, own group
         double psi_n1 = 0.0, sig_n1 = 0.0, lam_n1 = 1.0;
         if (i + 1 < I && real) {
@@ -178,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             T er = (T)1, so = (T)0, si = (T)0;
 #pragma unroll
             for (int kp = 0; kp < NT; ++kp) {
-                if (kp > 0) er = (kp > k) ? er * L.dd[kp - 1] : (T)1;
+                if (kp > 0) er = (kp > kz) ? er * L.dd[kp - 1] : (T)1;
                 const T po = Prow[kp] * er;
                 so = fma(po, (T)1 - L.bc[kp], so);
                 acc[kp] = fma(cap, po, acc[kp]);           // - c dt psi_k K^out_{kk'}
@@ -187,21 +213,27 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             T el = (T)1;
 #pragma unroll
             for (int kp = NT - 1; kp >= 0; --kp) {
-                el = (kp < k) ? el * L.dd[kp] : (T)1;
+                el = (kp < kz) ? el * L.dd[kp] : (T)1;
                 const T pi = Prow[kp] * el;
                 si = fma(pi, L.bc[kp], si);
                 acc[kp] = fma(cam, pi, acc[kp]);           // - c dt (1 - psi_k) K^in_{kk'}
             }
             diag += c * amp * (double)(si + so);
         }
-        if (real) {
+        // the diagonal: added here for the transposed or partially pivoted elimination; with diagonal
+        // pivots it is added by the owning lane at its own elimination step (entry (k,k) is read by
+        // nobody before that step, and the updates before it do not depend on it)
+        T dg = real ? (T)diag : (T)1;
+        if (TRANS || PIVOT) {
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) acc[kp] += (kp == k) ? (T)diag : (T)0;
-        } else {
+            for (int kp = 0; kp < NT; ++kp) acc[kp] = real ? acc[kp] + ((kp == kz) ? dg : (T)0)
+                                                          : ((kp == kz) ? (T)1 : (T)0);
+            dg = (T)0;
+        } else if (!real) {
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) acc[kp] = (kp == k) ? (T)1 : (T)0;   // padded identity row
-            bm = bp = bm_next = 0.0;
+            for (int kp = 0; kp < NT; ++kp) acc[kp] = (T)0;                       // padded identity row
         }
+        if (!real) bm = bp = bm_next = 0.0;
 
         // ---- right-hand side (and, for the transpose, the transposed block plus its Schur update)
         T g = real ? (T)(A.rhs_sign * rhs[(size_t)i * N + kk]) : (T)0;
@@ -223,57 +255,92 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             bcoef = (T)bm_next;
         }
 
-        // ---- in-place Gauss-Jordan with partial pivoting on [Ahat | diag(b) | g]
-        bool used = !is_row;
-        T mypiv = (T)1;
-        int mycol = 0;
+        // ---- in-place Gauss-Jordan on [Ahat | diag(b) | g]
+        if constexpr (PIVOT) {
+            // partial pivoting: packed-key max over the group, row ownership left permuted
+            bool used = !is_row;
+            T mypiv = (T)1;
+            int mycol = 0;
 #pragma unroll
-        for (int cc = 0; cc < NT; ++cc) {
-            const T ac = a[cc];
-            const uint32_t key =
-                used ? 0u : ((abs_key_bits(ac) & ~(uint32_t)(SL - 1)) | (uint32_t)(SL - 1 - k));
-            const uint32_t kmax = group_max<SL>(key);
-            const int p = SL - 1 - (int)(kmax & (SL - 1));
-            const bool isp = (k == p);
-            if (isp) {
+            for (int cc = 0; cc < NT; ++cc) {
+                const T ac = a[cc];
+                const uint32_t key =
+                    used ? 0u : ((abs_key_bits(ac) & ~(uint32_t)(SL - 1)) | (uint32_t)(SL - 1 - k));
+                const uint32_t kmax = group_max<SL>(key);
+                const int p = SL - 1 - (int)(kmax & (SL - 1));
+                const bool isp = (k == p);
+                if (isp) {
 #pragma unroll
-                for (int j = 0; j < NT; ++j) L.prow[j] = a[j];
-                L.prow[NT] = g;
-                L.prow[NT + 1] = bcoef;
+                    for (int j = 0; j < NT; ++j) L.prow[j] = a[j];
+                    L.prow[NT] = g;
+                    L.prow[NT + 1] = bcoef;
+                }
+                wave_sync();
+                const T piv = L.prow[cc];
+                zp |= (piv == (T)0);
+                const T pinv = rcp_nr(piv);
+                const T f = isp ? (T)0 : ac * pinv;
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    if (j != cc) a[j] = fma(-f, L.prow[j], a[j]);
+                g = fma(-f, L.prow[NT], g);
+                const T bpiv = L.prow[NT + 1];
+                a[cc] = isp ? bpiv : -f * bpiv;
+                if (isp) {
+                    used = true;
+                    mypiv = piv;
+                    mycol = cc;
+                }
+                wave_sync();
+            }
+            // restore row ownership: the lane holding unknown mycol writes its scaled row in slot
+            // order; slot sidx[m] (the step at which lane m was the pivot) holds column m of C
+            if (is_row) {
+                const T ip = rcp_nr(mypiv);
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) L.fix[mycol][cc] = a[cc] * ip;
+                L.fix[mycol][NT] = g * ip;
+                L.sidx[k] = mycol;
             }
             wave_sync();
-            const T piv = L.prow[cc];
-            zp |= (piv == (T)0);
-            const T pinv = (T)1 / piv;
-            const T f = isp ? (T)0 : ac * pinv;
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                if (j != cc) a[j] = fma(-f, L.prow[j], a[j]);
-            g = fma(-f, L.prow[NT], g);
-            const T bpiv = L.prow[NT + 1];
-            a[cc] = isp ? bpiv : -f * bpiv;
-            if (isp) {
-                used = true;
-                mypiv = piv;
-                mycol = cc;
-            }
+            for (int m = 0; m < NT; ++m) a[m] = is_row ? L.fix[kr][L.sidx[m]] : (T)0;
+            ycar = is_row ? L.fix[kr][NT] : (T)0;
             wave_sync();
-        }
-
-        // ---- restore row ownership: the lane holding unknown mycol writes its scaled row in slot
-        //      order; slot sidx[m] (the step at which lane m was the pivot) holds column m of C
-        if (is_row) {
-            const T ip = (T)1 / mypiv;
+        } else {
+            // diagonal pivots: step cc eliminates with row cc, so rows stay in natural order
+            T mypiv = (T)1;
 #pragma unroll
-            for (int cc = 0; cc < NT; ++cc) L.fix[mycol][cc] = a[cc] * ip;
-            L.fix[mycol][NT] = g * ip;
-            L.sidx[k] = mycol;
-        }
-        wave_sync();
+            for (int cc = 0; cc < NT; ++cc) {
+                const bool isp = (kz == cc);
+                if (isp) a[cc] += dg;                     // own diagonal, see above
+                const T ac = a[cc];
+                if (isp) {
 #pragma unroll
-        for (int m = 0; m < NT; ++m) a[m] = is_row ? L.fix[kr][L.sidx[m]] : (T)0;
-        ycar = is_row ? L.fix[kr][NT] : (T)0;
-        wave_sync();
+                    for (int j = 0; j < NT; ++j) L.prow[j] = a[j];
+                    L.prow[NT] = g;
+                    L.prow[NT + 1] = bcoef;
+                }
+                wave_sync();
+                const T piv = L.prow[cc];
+                const T pinv = rcp_nr(piv);
+                const T f = isp ? (T)0 : ac * pinv;
+                growth = fmax(growth, fabs(f));
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    if (j != cc) a[j] = fma(-f, L.prow[j], a[j]);
+                g = fma(-f, L.prow[NT], g);
+                const T bpiv = L.prow[NT + 1];
+                a[cc] = isp ? bpiv : -f * bpiv;
+                mypiv = isp ? piv : mypiv;
+                wave_sync();
+            }
+            zp |= !(fabs(mypiv) > (T)0) || !isfinite(mypiv);
+            const T ip = rcp_nr(mypiv);
+#pragma unroll
+            for (int m = 0; m < NT; ++m) a[m] = is_row ? a[m] * ip : (T)0;
+            ycar = is_row ? g * ip : (T)0;
+        }
 
         if (store) {
             T* Cz = wsC + (size_t)i * NT * NT;
@@ -291,9 +358,20 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         bp_prev = bp;
     }
 
-    // zero-pivot report (any lane of the system)
-    const uint32_t zany = group_max<SL>(zp ? 1u : 0u);
-    if (live && k == 0 && zany && A.flags) A.flags[sys] |= 4;
+    // zero-pivot report and, for diagonal pivots, the growth guard (any lane of the system)
+    const bool lane_bad = is_row && (zp || !(growth <= (T)A.growth_limit));
+    const uint32_t any_bad = group_max<SL>(lane_bad ? 1u : 0u);
+    bool skip = false;
+    if constexpr (PIVOT) {
+        if (live && k == 0 && any_bad && A.flags) A.flags[sys] |= 4;
+    } else {
+        skip = any_bad != 0;                          // leave this system to the pivoting re-run
+        if (live && k == 0 && any_bad) {
+            if (A.guard) A.guard[sys] = 1;
+            if (A.flags) A.flags[sys] |= 8;
+        }
+    }
+    const bool store_out = store && !skip;
 
     // ---------------------------------------------------------------- backward sweep
     double* outp = A.psi_out ? A.psi_out + cell0 : nullptr;
@@ -322,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             for (int m = 0; m < NT; ++m) dl = fma(-cr[m], L.bc[m], dl);
             wave_sync();
         }
-        if (store) {
+        if (store_out) {
             const size_t ci = (size_t)i * N + k;
             if (outp) outp[ci] += (double)dl;
             else xp[ci] = (double)dl;
@@ -332,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         for (int m = 0; m < NT; ++m) cr[m] = crn[m];
         yv = yn;
     }
-    if (live && k == 0 && A.iters && A.psi_out) A.iters[sys] += 1;
+    if (live && !skip && k == 0 && A.iters && A.psi_out) A.iters[sys] += 1;
 }
 
 size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
@@ -342,35 +420,41 @@ size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
     return (size_t)I * NT * (NT + 1) * es;
 }
 
-template <typename T, int NT, bool TR>
+template <typename T, int NT, bool TR, bool PV>
 static void launch_t(const FactorArgs& a, hipStream_t st) {
     constexpr int SL = NT > 16 ? 32 : 16;
     constexpr int SPB = (kBlock / 64) * (64 / SL);
     const long long blocks = (a.nsys + SPB - 1) / SPB;
-    hipLaunchKernelGGL((k_factor<T, NT, TR>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_factor<T, NT, TR, PV>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
 }
 
-template <int NT>
-static void launch_nt(const FactorArgs& a, bool fp32, bool tr, hipStream_t st) {
-    if (fp32) {
-        if (tr) launch_t<float, NT, true>(a, st);
-        else launch_t<float, NT, false>(a, st);
+template <typename T, int NT>
+static void launch_tp(const FactorArgs& a, bool tr, bool pv, hipStream_t st) {
+    if (tr) {
+        if (pv) launch_t<T, NT, true, true>(a, st);
+        else launch_t<T, NT, true, false>(a, st);
     } else {
-        if (tr) launch_t<double, NT, true>(a, st);
-        else launch_t<double, NT, false>(a, st);
+        if (pv) launch_t<T, NT, false, true>(a, st);
+        else launch_t<T, NT, false, false>(a, st);
     }
 }
 
-hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, hipStream_t st) {
+template <int NT>
+static void launch_nt(const FactorArgs& a, bool fp32, bool tr, bool pv, hipStream_t st) {
+    if (fp32) launch_tp<float, NT>(a, tr, pv, st);
+    else launch_tp<double, NT>(a, tr, pv, st);
+}
+
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st) {
     switch (padded_groups(a.sh.N)) {
-        case 4: launch_nt<4>(a, fp32, transpose, st); break;
-        case 8: launch_nt<8>(a, fp32, transpose, st); break;
-        case 12: launch_nt<12>(a, fp32, transpose, st); break;
-        case 16: launch_nt<16>(a, fp32, transpose, st); break;
-        case 20: launch_nt<20>(a, fp32, transpose, st); break;
-        case 24: launch_nt<24>(a, fp32, transpose, st); break;
-        case 28: launch_nt<28>(a, fp32, transpose, st); break;
-        case 32: launch_nt<32>(a, fp32, transpose, st); break;
+        case 4: launch_nt<4>(a, fp32, transpose, pivot, st); break;
+        case 8: launch_nt<8>(a, fp32, transpose, pivot, st); break;
+        case 12: launch_nt<12>(a, fp32, transpose, pivot, st); break;
+        case 16: launch_nt<16>(a, fp32, transpose, pivot, st); break;
+        case 20: launch_nt<20>(a, fp32, transpose, pivot, st); break;
+        case 24: launch_nt<24>(a, fp32, transpose, pivot, st); break;
+        case 28: launch_nt<28>(a, fp32, transpose, pivot, st); break;
+        case 32: launch_nt<32>(a, fp32, transpose, pivot, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

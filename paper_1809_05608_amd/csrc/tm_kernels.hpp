@@ -35,6 +35,8 @@ struct FactorArgs {
     const int* active;        // per system (global index), nullable = all active
     int* flags;               // per system, zero-pivot bit (nullable)
     int* iters;               // per system, incremented on update (nullable)
+    int* guard;               // per system, set to 1 when the growth guard trips (nullable)
+    double growth_limit;      // largest |multiplier| accepted with diagonal pivots
     void* wsC;                // [batch][I][NT][NT] factors (element type of the kernel)
     void* wsY;                // [batch][I][NT]
     long long sys0;           // first system of the batch
@@ -50,7 +52,7 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
 hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                          double* blocks, hipStream_t st);
 
-hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, hipStream_t st);
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st);
 
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,
@@ -59,6 +61,9 @@ hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const 
 hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, double* seed, hipStream_t st);
 
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
+
+// active_out[j] = 1 where guard[j] != 0 (else 0); *count = number of such systems
+hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st);
 
 size_t factor_ws_bytes_per_system(int I, int N, bool fp32);
 int padded_groups(int N);

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
             out.active[sys] = (!stop && !bad && it < out.max_iter && res > 0.0) ? 1 : 0;
         }
         if (out.flags) {
-            int fl = out.flags[sys] & 4;   // keep zero-pivot bit from the factorisation
+            int fl = out.flags[sys] & (4 | 8);   // keep the factorisation's zero-pivot / fallback bits
             if (out.rtol > 0.0 && !reached) fl |= 1;
             if (bad) fl |= 2;
             out.flags[sys] = fl;
@@ -510,6 +510,24 @@ __global__ __launch_bounds__(kBlock) void k_count(const int* __restrict__ active
 
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st) {
     hipLaunchKernelGGL(k_count, dim3(1), dim3(kBlock), 0, st, active, n, count);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark(const int* __restrict__ guard, long long n, int* __restrict__ act,
+                                                 int* count) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (long long j = threadIdx.x; j < n; j += kBlock) {
+        const int v = guard[j] != 0;
+        act[j] = v;
+        s += v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *count = (int)s;
+}
+
+hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_mark, dim3(1), dim3(kBlock), 0, st, guard, n, active_out, count);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_ERR_INVALID_ARG", 2: "TM_ERR_HIP", 3: "TM_ERR
                 4: "TM_ERR_NOT_CONVERGED", 5: "TM_ERR_NONFINITE", 6: "TM_ERR_WORKSPACE"}
 TERM_DIFFUSION, TERM_EMABS, TERM_NES = 1, 2, 4
 PREC_FP64, PREC_MIXED = 0, 1
-FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_ZERO_PIVOT = 1, 2, 4
+FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_ZERO_PIVOT, FLAG_PIVOT_FALLBACK = 1, 2, 4, 8
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
             "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_status_string",

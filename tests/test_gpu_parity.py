@@ -283,3 +283,43 @@ def test_binding_rejects_bad_tensors():
         ctx.newton_step(f, w.psi_n, w.psi_n.float(), 1, 0.0)
     with pytest.raises(ValueError):
         ctx.newton_step(f, w.psi_n, w.psi_n[:, :1].clone(), 1, 0.0)
+
+
+# ------------------------------------------------------------------ pivoting policies
+
+@pytest.mark.parametrize("env", [dict(TM_PIVOT="always"), dict(TM_GROWTH_LIMIT="0"), dict(TM_PIVOT="auto")])
+@pytest.mark.parametrize("precision", [tm.PREC_FP64, tm.PREC_MIXED])
+def test_pivoting_policies_agree(monkeypatch, env, precision):
+    """Diagonal pivots (default), forced partial pivoting, and a growth guard of 0 (every
+    system takes the partial-pivoting re-run) all give the oracle's solve and Newton step."""
+    say("case pivot policy", env, precision)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    w = synth.make_custom(S=2, R=5, I=30, N=20)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd, precision)
+    rng = np.random.default_rng(13)
+    psi = w.psi_n.numpy() * 1.02
+    rhs = rng.standard_normal(psi.shape)
+    x = torch.empty(psi.shape, dtype=torch.float64, device="cuda")
+    ctx.factor_solve(f, torch.as_tensor(psi, device="cuda"), torch.as_tensor(rhs, device="cuda"), x, False)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    syss = oracle.systems_from_workload(w.numpy())
+    bar = 1e-11 if precision == tm.PREC_FP64 else 3e-4
+    for s in range(w.S):
+        for r in range(w.R):
+            A, bm, bp = oracle.jacobian_blocks(syss[s][r], psi[s, r])
+            xo = oracle.block_thomas_solve(A, bm, bp, rhs[s, r])
+            assert np.max(np.abs(x[s, r] - xo)) / np.max(np.abs(xo)) < bar
+    pd = wd.psi_n.clone()
+    st, stats = ctx.newton_step(f, wd.psi_n, pd, 30, 1e-12, raise_on_status=False)
+    torch.cuda.synchronize()
+    assert st == 0
+    ref, _ = oracle_newton(w, 30, 1e-12)
+    assert rel_err(pd.cpu().numpy(), ref) < (FP64_BAR if precision == tm.PREC_FP64 else MIXED_BAR)
+    fallback = stats["flags"].cpu().numpy() & tm.FLAG_PIVOT_FALLBACK
+    if env.get("TM_GROWTH_LIMIT") == "0":
+        assert np.all(fallback)
+    else:
+        assert not np.any(fallback)

@@ -83,9 +83,15 @@ struct alignas(16) SysLds {
 // without pivoting is stable.  A system whose multipliers exceed A.growth_limit, or that
 // meets a zero or non-finite pivot, is not updated and is marked in A.guard so that the
 // host can re-factor it with PIVOT = true (partial pivoting).
+// Lanes per system: partial pivoting reduces the pivot key with DPP row operations and needs
+// power-of-two groups (16 or 32 lanes); diagonal pivots only talk through LDS, so a system
+// takes exactly NT lanes and a wave64 holds floor(64/NT) systems (3 at N = 20).
+template <int NT, bool PIVOT>
+constexpr int lanes_per_system() { return PIVOT ? (NT > 16 ? 32 : 16) : NT; }
+
 template <typename T, int NT, bool TRANS, bool PIVOT>
 __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
-    constexpr int SL = NT > 16 ? 32 : 16;
+    constexpr int SL = lanes_per_system<NT, PIVOT>();
     constexpr int SPW = 64 / SL;
     constexpr int SPB = (kBlock / 64) * SPW;
     __shared__ SysLds<T, NT> lds_all[SPB];
@@ -95,12 +101,14 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int sub = lane / SL, k = lane % SL;
+    const bool in_group = lane < SPW * SL;                                   // lanes past the last group idle
+    const int sub = in_group ? lane / SL : SPW - 1;
+    const int k = in_group ? lane % SL : SL;                                 // idle lanes own no row
     const long long sb = (long long)blockIdx.x * SPB + wave * SPW + sub;    // system within the batch
     const bool in_batch = sb < A.nsys;
     const long long sbc = in_batch ? sb : A.nsys - 1;                        // clamped for loads
     const long long sys = A.sys0 + sbc;                                      // global system index
-    const bool live = in_batch && (A.active == nullptr || A.active[sys] != 0);
+    const bool live = in_group && in_batch && (A.active == nullptr || A.active[sys] != 0);
     if (__ballot(live) == 0) return;                                         // whole wave idle
 
     SysLds<T, NT>& L = lds_all[wave * SPW + sub];
@@ -110,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     const bool real = k < N;         // owns a real energy-group row
     const int kk = real ? k : 0;     // safe group index for loads
     const int kr = is_row ? k : 0;   // safe row index for LDS
+    const int kp_safe = k < kMaxN ? k : 0;
     const int ray = (int)(sys % sh.R);
     const double* re = A.f.r_edge + (size_t)ray * (I + 1);
     const size_t cell0 = (size_t)sys * I * N;
@@ -127,7 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     const bool store = live && real;
 
     const T* Prow = s_P + kr * PS;                  // row k of the NES shape (zero outside N x N)
-    const double de_k = A.cs->de[k < kMaxN ? k : 0];
+    const double de_k = A.cs->de[kp_safe];
+    const double eps_k = A.cs->eps[kp_safe];
 
     // ---------------------------------------------------------------- forward sweep
     T a[NT];
@@ -192,33 +202,60 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         if (nes) {
             const double amp = az[i];
             const double Tz = tz[i];
-            if (is_row) {
-                L.bc[k] = real ? (T)psi_c : (T)0;
-                L.dd[k] = (k + 1 < N) ? texp((T)(-de_k / Tz)) : (T)0;
-            }
-            wave_sync();
             const T pk = (T)psi_c;
             const T ca = (T)(-c * amp);
-            const T cap = ca * pk, cam = ca * ((T)1 - pk);
-            // out factor: exp(-(eps_k' - eps_k)/T) for k' > k, 1 otherwise (ascending product)
-            T er = (T)1, so = (T)0, si = (T)0;
+            if constexpr (sizeof(T) == 4) {
+                // FP32 Jacobian: exp(-|eps_k - eps_k'|/T) directly with the hardware exp2, all k' at once;
+                // with M = that factor the NES entry is ca P (1 + w (M - 1)), w = psi_k above the diagonal
+                // and 1 - psi_k below it, and the diagonal sum is P (1 + v (M - 1)), v = 1 - psi_k' above
+                // and psi_k' below
+                const float sc = (float)(1.4426950408889634 / Tz);
+                if (is_row) {
+                    L.bc[k] = real ? (T)psi_c : (T)0;
+                    L.dd[k] = (float)eps_k * sc;
+                }
+                wave_sync();
+                const float xk = (float)eps_k * sc;
+                T ds = (T)0;
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) {
-                if (kp > 0) er = (kp > kz) ? er * L.dd[kp - 1] : (T)1;
-                const T po = Prow[kp] * er;
-                so = fma(po, (T)1 - L.bc[kp], so);
-                acc[kp] = fma(cap, po, acc[kp]);           // - c dt psi_k K^out_{kk'}
-            }
-            // in factor: exp(-(eps_k - eps_k')/T) for k' < k, 1 otherwise (descending product)
-            T el = (T)1;
+                for (int kp = 0; kp < NT; ++kp) {
+                    const float d = L.dd[kp] - xk;           // > 0 above the diagonal
+                    const float tM = __builtin_amdgcn_exp2f(-fabsf(d)) - 1.0f;
+                    const float pp = L.bc[kp];
+                    const bool up = d > 0.0f;
+                    const float w = up ? pk : 1.0f - pk;
+                    const float v = up ? 1.0f - pp : pp;
+                    acc[kp] = fma(ca * Prow[kp], fma(w, tM, 1.0f), acc[kp]);
+                    ds = fma(Prow[kp], fma(v, tM, 1.0f), ds);
+                }
+                diag += c * amp * (double)ds;
+            } else {
+                if (is_row) {
+                    L.bc[k] = real ? (T)psi_c : (T)0;
+                    L.dd[k] = (k + 1 < N) ? texp((T)(-de_k / Tz)) : (T)0;
+                }
+                wave_sync();
+                const T cap = ca * pk, cam = ca * ((T)1 - pk);
+                // out factor: exp(-(eps_k' - eps_k)/T) for k' > k, 1 otherwise (ascending product)
+                T er = (T)1, so = (T)0, si = (T)0;
 #pragma unroll
-            for (int kp = NT - 1; kp >= 0; --kp) {
-                el = (kp < kz) ? el * L.dd[kp] : (T)1;
-                const T pi = Prow[kp] * el;
-                si = fma(pi, L.bc[kp], si);
-                acc[kp] = fma(cam, pi, acc[kp]);           // - c dt (1 - psi_k) K^in_{kk'}
+                for (int kp = 0; kp < NT; ++kp) {
+                    if (kp > 0) er = (kp > kz) ? er * L.dd[kp - 1] : (T)1;
+                    const T po = Prow[kp] * er;
+                    so = fma(po, (T)1 - L.bc[kp], so);
+                    acc[kp] = fma(cap, po, acc[kp]);           // - c dt psi_k K^out_{kk'}
+                }
+                // in factor: exp(-(eps_k - eps_k')/T) for k' < k, 1 otherwise (descending product)
+                T el = (T)1;
+#pragma unroll
+                for (int kp = NT - 1; kp >= 0; --kp) {
+                    el = (kp < kz) ? el * L.dd[kp] : (T)1;
+                    const T pi = Prow[kp] * el;
+                    si = fma(pi, L.bc[kp], si);
+                    acc[kp] = fma(cam, pi, acc[kp]);           // - c dt (1 - psi_k) K^in_{kk'}
+                }
+                diag += c * amp * (double)(si + so);
             }
-            diag += c * amp * (double)(si + so);
         }
         // the diagonal: added here for the transposed or partially pivoted elimination; with diagonal
         // pivots it is added by the owning lane at its own elimination step (entry (k,k) is read by
@@ -360,7 +397,14 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
 
     // zero-pivot report and, for diagonal pivots, the growth guard (any lane of the system)
     const bool lane_bad = is_row && (zp || !(growth <= (T)A.growth_limit));
-    const uint32_t any_bad = group_max<SL>(lane_bad ? 1u : 0u);
+    uint32_t any_bad;
+    if constexpr (PIVOT) {
+        any_bad = group_max<SL>(lane_bad ? 1u : 0u);
+    } else {
+        const unsigned long long b = __ballot(lane_bad);
+        const unsigned long long gm = (SL == 64) ? ~0ull : ((1ull << SL) - 1ull);
+        any_bad = ((b >> (sub * SL)) & gm) != 0ull;
+    }
     bool skip = false;
     if constexpr (PIVOT) {
         if (live && k == 0 && any_bad && A.flags) A.flags[sys] |= 4;
@@ -422,7 +466,7 @@ size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
 
 template <typename T, int NT, bool TR, bool PV>
 static void launch_t(const FactorArgs& a, hipStream_t st) {
-    constexpr int SL = NT > 16 ? 32 : 16;
+    constexpr int SL = lanes_per_system<NT, PV>();
     constexpr int SPB = (kBlock / 64) * (64 / SL);
     const long long blocks = (a.nsys + SPB - 1) / SPB;
     hipLaunchKernelGGL((k_factor<T, NT, TR, PV>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);

@@ -197,9 +197,11 @@ tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
 
 /* Seed of the adjoint for the outer-boundary number luminosity
  *   L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}   (number through the outer surface, eq. a62)
- * written as a cell array: dL_N/dpsi = c R_{I+1/2}^2 W_k in the outermost zone, zero
- * elsewhere (zero everywhere without an outgoing flux).  Needs r_edge and e_edge only. */
-tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, double *seed);
+ * written as a cell array: seed = dL_N/dpsi + add, where dL_N/dpsi = c R_{I+1/2}^2 W_k in
+ * the outermost zone and zero elsewhere (zero everywhere without an outgoing flux).
+ * `add` (cell array) may be NULL or alias `seed`; a multi-step adjoint passes the adjoint of
+ * the following step there.  Needs r_edge and e_edge only.                          */
+tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, const double *add, double *seed);
 
 /* Human-readable name of a status code (static storage).                          */
 const char *tm_status_string(tm_status status);

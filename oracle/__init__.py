@@ -19,5 +19,5 @@ from .transport import (  # noqa: F401
     System, systems_from_workload, group_energies, geometry, nes_kernels, edge_flux,
     residual, jacobian_blocks, dense_jacobian, block_thomas_solve, dense_solve,
     newton, step_stats, luminosity, luminosity_seed, adjoint, param_vjp,
-    newton_batch, residual_batch,
+    newton_batch, residual_batch, multistep_forward, multistep_objective, multistep_adjoint,
 )

@@ -338,41 +338,58 @@ class NewtonResult:
     history: list
 
 
+ARMIJO_C = 1e-4          # sufficient-decrease constant of the backtracking line search
+ALPHA_MIN = 2.0 ** -8    # shortest step tried before a step is taken regardless
+
+
 def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
            max_iter: int = 30, rtol: float = 0.0) -> NewtonResult:
     """Backward-Euler Newton iteration (eq. a62aa) for psi^{n+1} of one system.
 
-    Starts from psi0 (default psi^n).  Before each update the residual norm
-    r_m = max|G(psi^(m))| is compared with rtol * r_0; the iteration stops when
-    r_m <= rtol * r_0 or after max_iter updates.  Each update solves J delta = -G.
+    Starts from psi0 (default psi^n).  Each update solves J delta = -G (eq. a62ae) and is
+    globalised by backtracking on r = max|G|: the trial psi + delta is accepted when
+    r_trial <= (1 - 1e-4 alpha) r, else alpha is halved (the trial moved back by
+    (alpha_new - alpha) delta) down to alpha = 2^-8, which is taken regardless.  Within 1000x
+    of the target (the rounding level of G when rtol = 0) a full step is taken without the test.  The paper's scheme is plain
+    Newton; without the line search the strongly spiked stress rays diverge (psi overshoots
+    the Pauli limit 1 and the residual grows), with it they converge quadratically.
+    Stopping (rtol > 0): r <= target = max(rtol r_0, rounding level of G), or no halving of r
+    within 1000x of the target; rtol = 0 runs exactly max_iter updates.
     """
     psi = (psi_n if psi0 is None else psi0).copy()
-    hist = []
-    res0 = None
-    iters = 0
-    prev = np.inf
-    for _ in range(max_iter):
-        G = residual(sys, psi_n, psi)
-        r = float(np.max(np.abs(G)))
-        hist.append(r)
-        if res0 is None:
-            res0 = r
-        if r == 0.0:
-            break
-        if rtol > 0.0:
-            target = max(rtol * res0, residual_rounding_level(sys, psi_n, psi))
-            if r <= target or (r <= 1e3 * target and r > 0.5 * prev):
-                break          # reached, or stalled: the update is below the resolution of psi
-        prev = r
-        blocks, bm, bp = jacobian_blocks(sys, psi)
-        psi = psi + block_thomas_solve(blocks, bm, bp, -G)
-        iters += 1
     G = residual(sys, psi_n, psi)
     r = float(np.max(np.abs(G)))
-    if res0 is None:
-        res0 = r
-    hist.append(r)
-    conv = r <= max(rtol * res0, residual_rounding_level(sys, psi_n, psi)) if rtol > 0.0 else True
+    res0 = r
+    hist = [r]
+    iters = 0
+    prev = np.inf
+    target = 0.0
+    for _ in range(max_iter):
+        if r == 0.0 or not np.isfinite(r):
+            break
+        target = max(rtol * res0, residual_rounding_level(sys, psi_n, psi))
+        if rtol > 0.0 and (r <= target or (r <= 1e3 * target and r > 0.5 * prev)):
+            break              # reached, or stalled: the update is below the resolution of psi
+        blocks, bm, bp = jacobian_blocks(sys, psi)
+        delta = block_thomas_solve(blocks, bm, bp, -G)
+        iters += 1
+        trial = psi + delta
+        alpha = 1.0
+        Gt = residual(sys, psi_n, trial)
+        rt = float(np.max(np.abs(Gt)))
+        near = r <= 1e3 * target
+        while not near and not rt <= (1.0 - ARMIJO_C * alpha) * r and alpha > ALPHA_MIN:
+            alpha_new = 0.5 * alpha
+            trial = trial + (alpha_new - alpha) * delta
+            alpha = alpha_new
+            Gt = residual(sys, psi_n, trial)
+            rt = float(np.max(np.abs(Gt)))
+        prev = r
+        psi, G, r = trial, Gt, rt
+        hist.append(r)
+    if rtol > 0.0:
+        target = max(rtol * res0, residual_rounding_level(sys, psi_n, psi))
+    conv = (r <= target) if rtol > 0.0 else True
     return NewtonResult(psi=psi, iters=iters, res0=res0, res=r, converged=bool(conv), history=hist)
 
 
@@ -523,3 +540,39 @@ def residual_batch(w: dict, psi: np.ndarray) -> np.ndarray:
         for r in range(w["R"]):
             G[s, r] = residual(syss[s][r], w["psi_n"][s, r], psi[s, r])
     return G
+
+
+# ---------------------------------------------------------------- multi-step objective and adjoint
+
+def multistep_forward(systems: list, psi0: np.ndarray, max_iter: int = 40, rtol: float = 1e-14) -> list:
+    """psi^1..psi^S of S consecutive implicit steps; step s uses systems[s] and psi^n = psi^{s-1}."""
+    out = []
+    psi = psi0
+    for sysm in systems:
+        psi = newton(sysm, psi, max_iter=max_iter, rtol=rtol).psi
+        out.append(psi)
+    return out
+
+
+def multistep_objective(systems: list, psis: list) -> float:
+    """J = sum_s L_N(psi^s): the number leaving the outer surface over the steps (dt dropped)."""
+    return float(sum(luminosity(sy, p) for sy, p in zip(systems, psis)))
+
+
+def multistep_adjoint(systems: list, psis: list):
+    """Reverse recursion for J = sum_s L_N(psi^s).
+
+    With lambda_s the total derivative of J with respect to psi^s,
+      lambda_S = dL/dpsi^S,  J_s^T mu_s = lambda_s,  lambda_{s-1} = dL/dpsi^{s-1} + mu_s
+    (psi^{s-1} enters step s only as psi^n, and dG_s/dpsi^n = -1), so dJ/dpsi^0 = mu_1 and
+    dJ/dtheta_s = -mu_s^T dG_s/dtheta_s.  Returns (dJ/dpsi^0, [param_vjp of each step]).
+    """
+    S = len(systems)
+    grads = [None] * S
+    mu_next = np.zeros_like(psis[0])
+    for s in range(S - 1, -1, -1):
+        seed = luminosity_seed(systems[s], psis[s].shape) + mu_next
+        mu = adjoint(systems[s], psis[s], seed)
+        grads[s] = param_vjp(systems[s], psis[s], mu)
+        mu_next = mu
+    return mu_next, grads

@@ -33,6 +33,12 @@ struct tm_ctx {
     double* gbuf = nullptr;     // [cells] residual for the Newton right-hand side
     int* h_count = nullptr;     // pinned host
     int* guard = nullptr;       // [nsys] growth guard of the last diagonal-pivot launch
+    double* res_acc = nullptr;  // [nsys] Newton line search: accepted residual
+    double* tgt = nullptr;      // [nsys] stopping target at the accepted iterate
+    double* alpha = nullptr;    // [nsys] step length of the pending trial
+    int* pending = nullptr;     // [nsys] trial under evaluation
+    int* backtrack = nullptr;   // [nsys] trial rejected
+    double* dbuf = nullptr;     // [cells] Newton update delta (for backtracking)
     int* redo = nullptr;        // [nsys] systems re-factored with partial pivoting
     // pivoting policy: 0 diagonal pivots with guarded fallback to partial pivoting (default),
     // 1 always partial pivoting, 2 diagonal pivots only (guard trips become failures)
@@ -131,12 +137,20 @@ tm_status ensure_small(tm_ctx* c) {
     TM_TRY(hip_check(c, hipHostMalloc((void**)&c->h_count, sizeof(int)), "hipHostMalloc"));
     TM_TRY(hip_check(c, hipMalloc((void**)&c->guard, ns * sizeof(int)), "hipMalloc guard"));
     TM_TRY(hip_check(c, hipMalloc((void**)&c->redo, ns * sizeof(int)), "hipMalloc redo"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->res_acc, ns * sizeof(double)), "hipMalloc res_acc"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->tgt, ns * sizeof(double)), "hipMalloc tgt"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->alpha, ns * sizeof(double)), "hipMalloc alpha"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->pending, ns * sizeof(int)), "hipMalloc pending"));
+    TM_TRY(hip_check(c, hipMalloc((void**)&c->backtrack, ns * sizeof(int)), "hipMalloc backtrack"));
     return TM_OK;
 }
 
 tm_status ensure_gbuf(tm_ctx* c) {
-    if (c->gbuf) return TM_OK;
-    return hip_check(c, hipMalloc((void**)&c->gbuf, n_cells(c->p) * sizeof(double)), "hipMalloc residual buffer");
+    if (!c->gbuf)
+        TM_TRY(hip_check(c, hipMalloc((void**)&c->gbuf, n_cells(c->p) * sizeof(double)), "hipMalloc residual buffer"));
+    if (!c->dbuf)
+        TM_TRY(hip_check(c, hipMalloc((void**)&c->dbuf, n_cells(c->p) * sizeof(double)), "hipMalloc update buffer"));
+    return TM_OK;
 }
 
 // Systems per factor launch that fit the workspace; allocates all-systems workspace if none.
@@ -165,7 +179,8 @@ tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
 }
 
 tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double rhs_sign,
-                     double* x, double* psi_out, const int* active, bool fp32, bool transpose) {
+                     double* x, double* psi_out, const int* active, bool fp32, bool transpose,
+                     double* dx = nullptr) {
     long long batch = 0;
     TM_TRY(factor_batch(c, fp32, &batch));
     const int NT = tmk::padded_groups(c->p.n_groups);
@@ -184,6 +199,9 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     a.iters = psi_out ? c->iters : nullptr;
     a.guard = c->guard;
     a.growth_limit = c->growth_limit;
+    a.dx = psi_out ? dx : nullptr;
+    a.pending = psi_out ? c->pending : nullptr;
+    a.alpha = psi_out ? c->alpha : nullptr;
     a.wsC = c->ws;
     a.wsY = (char*)c->ws + (size_t)batch * c->p.n_zones * NT * NT * es;
     const long long ns = n_systems(c->p);
@@ -277,8 +295,14 @@ tm_status tm_destroy(tm_ctx* c) {
         (void)hipHostFree(c->h_count);
         (void)hipFree(c->guard);
         (void)hipFree(c->redo);
+        (void)hipFree(c->res_acc);
+        (void)hipFree(c->tgt);
+        (void)hipFree(c->alpha);
+        (void)hipFree(c->pending);
+        (void)hipFree(c->backtrack);
     }
     if (c->gbuf) (void)hipFree(c->gbuf);
+    if (c->dbuf) (void)hipFree(c->dbuf);
     if (c->ws && c->ws_owned) (void)hipFree(c->ws);
     delete c;
     return TM_OK;
@@ -310,6 +334,7 @@ tm_status tm_assemble(tm_ctx* c, const tm_inputs* in, const double* psi_n, const
     const tmk::Fields f = fields_of(*in);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
     tmk::ResidualOut o{};
+    o.mode = tmk::kResPlain;
     o.res = c->res;
     TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, residual, 1.0, o, c->stream),
                      "residual kernel"));
@@ -346,35 +371,54 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
     TM_TRY(hip_check(c, hipMemsetAsync(c->iters, 0, ns * sizeof(int), c->stream), "memset iters"));
     TM_TRY(hip_check(c, hipMemsetAsync(c->flags, 0, ns * sizeof(int), c->stream), "memset flags"));
 
-    for (int it = 0; it <= max_iter; ++it) {
-        tmk::ResidualOut o{};
-        o.res = c->res;
-        o.res0 = c->res0;
-        o.set_res0 = it == 0;
-        o.skip_inactive = it > 0;
-        o.active = c->active;
-        o.iters = c->iters;
-        o.max_iter = max_iter;
-        o.rtol = rtol;
-        TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, c->gbuf, 1.0, o, c->stream),
-                         "residual kernel"));
-        if (it == max_iter) break;
-        TM_TRY(hip_check(c, tmk::launch_count_active(c->active, ns, c->count, c->stream), "count kernel"));
+    auto count_of = [&](const int* flags_arr, int* out_n) -> tm_status {
+        TM_TRY(hip_check(c, tmk::launch_count_active(flags_arr, ns, c->count, c->stream), "count kernel"));
         TM_TRY(hip_check(c, hipMemcpyAsync(c->h_count, c->count, sizeof(int), hipMemcpyDeviceToHost, c->stream),
                          "copy count"));
         TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
-        if (*c->h_count == 0) break;
-        TM_TRY(run_factor(c, in, psi, c->gbuf, -1.0, nullptr, psi, c->active, fp32, false));
-    }
-
-    // final statistics at the returned psi
+        *out_n = *c->h_count;
+        return TM_OK;
+    };
     tmk::ResidualOut o{};
     o.res = c->res;
     o.res0 = c->res0;
-    o.set_res0 = 0;
-    o.flags = c->flags;
-    o.rtol = rtol;
+    o.res_acc = c->res_acc;
+    o.tgt = c->tgt;
+    o.alpha = c->alpha;
+    o.pending = c->pending;
+    o.backtrack = c->backtrack;
+    o.active = c->active;
+    o.iters = c->iters;
     o.max_iter = max_iter;
+    o.rtol = rtol;
+    TM_TRY(hip_check(c, hipMemsetAsync(c->pending, 0, ns * sizeof(int), c->stream), "memset pending"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->backtrack, 0, ns * sizeof(int), c->stream), "memset backtrack"));
+    o.mode = tmk::kResInitial;
+    TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, c->gbuf, 1.0, o, c->stream),
+                     "residual kernel"));
+    const int max_trials = 9;                              // alpha = 1, 1/2, ..., 1/256
+    for (int it = 0; it < max_iter; ++it) {
+        int nact = 0;
+        TM_TRY(count_of(c->active, &nact));
+        if (nact == 0) break;
+        // Newton update psi += delta for the active systems (delta kept for backtracking)
+        TM_TRY(run_factor(c, in, psi, c->gbuf, -1.0, nullptr, psi, c->active, fp32, false, c->dbuf));
+        // line search on max|G| with the FP64 residual; a rejected trial is moved back to half the step
+        o.mode = tmk::kResTrial;
+        for (int t = 0; t < max_trials; ++t) {
+            TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, c->gbuf, 1.0, o, c->stream),
+                             "residual kernel"));
+            int nback = 0;
+            TM_TRY(count_of(c->backtrack, &nback));
+            if (nback == 0) break;
+            TM_TRY(hip_check(c, tmk::launch_backtrack(sh, psi, c->dbuf, c->backtrack, c->alpha, c->stream),
+                             "backtrack kernel"));
+        }
+    }
+
+    // final flags and statistics at the returned psi
+    o.mode = tmk::kResFinal;
+    o.flags = c->flags;
     o.stats = stats != nullptr;
     if (stats) {
         o.n_tot = stats->n_tot;
@@ -426,14 +470,14 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
     return TM_OK;
 }
 
-tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, double* seed) {
+tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, double* seed) {
     if (!c) return TM_ERR_INVALID_ARG;
     if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
     if (!seed) return set_err(c, TM_ERR_INVALID_ARG, "seed is required");
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
-    return hip_check(c, tmk::launch_lum_seed(sh, in->r_edge, c->consts, seed, c->stream), "seed kernel");
+    return hip_check(c, tmk::launch_lum_seed(sh, in->r_edge, c->consts, add, seed, c->stream), "seed kernel");
 }
 
 }  // extern "C"

@@ -420,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     // ---------------------------------------------------------------- backward sweep
     double* outp = A.psi_out ? A.psi_out + cell0 : nullptr;
     double* xp = A.x ? A.x + cell0 : nullptr;
+    double* dxp = A.dx ? A.dx + cell0 : nullptr;
     T cr[NT], crn[NT];
     T yv = (T)0, yn = (T)0;
     {
@@ -446,15 +447,23 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
         if (store_out) {
             const size_t ci = (size_t)i * N + k;
-            if (outp) outp[ci] += (double)dl;
-            else xp[ci] = (double)dl;
+            if (outp) {
+                outp[ci] += (double)dl;
+                if (dxp) dxp[ci] = (double)dl;
+            } else {
+                xp[ci] = (double)dl;
+            }
         }
         dnext = dl;
 #pragma unroll
         for (int m = 0; m < NT; ++m) cr[m] = crn[m];
         yv = yn;
     }
-    if (live && !skip && k == 0 && A.iters && A.psi_out) A.iters[sys] += 1;
+    if (live && !skip && k == 0 && A.psi_out) {
+        if (A.iters) A.iters[sys] += 1;
+        if (A.pending) A.pending[sys] = 1;               // trial psi + delta awaits the line search
+        if (A.alpha) A.alpha[sys] = 1.0;
+    }
 }
 
 size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {

@@ -5,20 +5,36 @@
 
 namespace tmk {
 
-// Outputs of the residual / statistics kernel, all per system of the launch.
+// Newton line-search constants (sufficient decrease, shortest step) shared with the host.
+constexpr double kArmijo = 1e-4;
+constexpr double kAlphaMin = 1.0 / 256.0;
+
+// Residual pass modes.
+enum ResidualMode : int {
+    kResPlain = 0,      // max|G| only (tm_assemble)
+    kResInitial = 1,    // first Newton pass: res0, accepted residual, target, activity
+    kResTrial = 2,      // pending trials only: accept (stopping rule, activity) or ask to backtrack
+    kResFinal = 3,      // flags and conservation statistics at the returned state
+};
+
+// Inputs/outputs of the residual / statistics kernel, all per system of the launch.
 struct ResidualOut {
-    double* res;        // max |G|                       (required)
-    double* res0;       // written when set_res0 != 0     (nullable)
-    int* active;        // Newton activity flag           (nullable)
-    const int* iters;   // updates applied so far         (nullable)
-    int* flags;         // TM_FLAG_* bits                 (nullable)
-    double* n_tot;      // statistics, written when stats != 0 (nullable)
+    int mode;
+    double* res;        // max |G| of the evaluated state (required)
+    double* res0;       // max |G| at the initial guess
+    double* res_acc;    // max |G| of the accepted iterate
+    double* tgt;        // stopping target max(rtol res0, rounding level) at the accepted iterate
+    double* alpha;      // step length of the pending trial
+    int* pending;       // 1 while a trial is under evaluation
+    int* backtrack;     // set to 1 when the trial is rejected
+    int* active;        // Newton activity flag
+    const int* iters;   // updates applied so far
+    int* flags;         // TM_FLAG_* bits (final pass)
+    double* n_tot;      // statistics (final pass, nullable)
     double* e_tot;
     double* budget;
     double* lum;
-    int set_res0;
     int stats;
-    int skip_inactive;  // systems with active == 0 are left untouched (Newton iterations after the first)
     int max_iter;
     double rtol;
 };
@@ -36,6 +52,9 @@ struct FactorArgs {
     int* flags;               // per system, zero-pivot bit (nullable)
     int* iters;               // per system, incremented on update (nullable)
     int* guard;               // per system, set to 1 when the growth guard trips (nullable)
+    double* dx;               // Newton: the update delta is also written here (nullable)
+    int* pending;             // Newton: set to 1 for updated systems (trial to evaluate)
+    double* alpha;            // Newton: set to 1 for updated systems
     double growth_limit;      // largest |multiplier| accepted with diagonal pivots
     void* wsC;                // [batch][I][NT][NT] factors (element type of the kernel)
     void* wsY;                // [batch][I][NT]
@@ -58,9 +77,14 @@ hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const 
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,
                       hipStream_t st);
 
-hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, double* seed, hipStream_t st);
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
+                           hipStream_t st);
 
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
+
+// psi += (alpha/2 - alpha) dx and alpha /= 2 for systems with backtrack set (which is cleared)
+hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int* backtrack, double* alpha,
+                            hipStream_t st);
 
 // active_out[j] = 1 where guard[j] != 0 (else 0); *count = number of such systems
 hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st);

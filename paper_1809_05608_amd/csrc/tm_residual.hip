@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     __shared__ double s_d[ZB][PS];
     __shared__ double red[kBlock / 64];
     const long long sys = blockIdx.x;
-    if (out.skip_inactive && out.active && out.active[sys] == 0) return;   // converged before: unchanged
+    if (out.mode == kResTrial && out.pending[sys] == 0) return;         // no trial to evaluate
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
     const double* re = f.r_edge + (size_t)ray * (I + 1);
@@ -298,27 +298,44 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         s_b = block_sum(s_b, red);
     }
     if (threadIdx.x == 0) {
-        const double prev = out.set_res0 ? __builtin_inf() : out.res[sys];
-        out.res[sys] = bad ? __builtin_nan("") : res;
-        double r0 = res;
-        if (out.set_res0 && out.res0) out.res0[sys] = bad ? __builtin_nan("") : res;
-        else if (out.res0) r0 = out.res0[sys];
-        // Newton stopping rule: max|G| <= max(rtol * max|G_0|, rounding level of G), or no halving
-        // of max|G| within 1000x of that target (the update is below the resolution of psi);
-        // rtol = 0 means a fixed number of updates
-        const double target = fmax(out.rtol * r0, floor_g);
-        const bool reached = !bad && out.rtol > 0.0 && res <= target;
-        const bool stalled = !bad && out.rtol > 0.0 && res <= 1e3 * target && res > 0.5 * prev;
-        const bool stop = reached || stalled;
-        if (out.active) {
-            const int it = out.iters ? out.iters[sys] : 0;
-            out.active[sys] = (!stop && !bad && it < out.max_iter && res > 0.0) ? 1 : 0;
-        }
-        if (out.flags) {
-            int fl = out.flags[sys] & (4 | 8);   // keep the factorisation's zero-pivot / fallback bits
-            if (out.rtol > 0.0 && !reached) fl |= 1;
-            if (bad) fl |= 2;
-            out.flags[sys] = fl;
+        const double rr = bad ? __builtin_nan("") : res;
+        out.res[sys] = rr;
+        const int it = out.iters ? out.iters[sys] : 0;
+        if (out.mode == kResInitial) {
+            // Newton stopping rule: max|G| <= target = max(rtol * max|G_0|, rounding level of G), or no
+            // halving of max|G| within 1000x of the target; rtol = 0 means a fixed number of updates
+            const double target = fmax(out.rtol * rr, floor_g);
+            out.res0[sys] = rr;
+            out.res_acc[sys] = rr;
+            out.tgt[sys] = target;
+            const bool stop = out.rtol > 0.0 && !bad && rr <= target;
+            out.active[sys] = (!stop && !bad && it < out.max_iter && rr > 0.0) ? 1 : 0;
+        } else if (out.mode == kResTrial) {
+            // backtracking line search: accept the trial on sufficient decrease of max|G|, at the
+            // shortest step, or when the previous iterate was already within 1000x of its target
+            const double racc = out.res_acc[sys], a = out.alpha[sys];
+            const bool near = racc <= 1e3 * out.tgt[sys];
+            const bool accept = near || rr <= (1.0 - kArmijo * a) * racc || a <= kAlphaMin;
+            if (accept) {
+                const double target = fmax(out.rtol * out.res0[sys], floor_g);
+                out.pending[sys] = 0;
+                out.backtrack[sys] = 0;
+                out.res_acc[sys] = rr;
+                out.tgt[sys] = target;
+                const bool stop = out.rtol > 0.0 && !bad && (rr <= target || (rr <= 1e3 * target && rr > 0.5 * racc));
+                out.active[sys] = (!stop && !bad && it < out.max_iter && rr > 0.0) ? 1 : 0;
+            } else {
+                out.backtrack[sys] = 1;
+            }
+        } else if (out.mode == kResFinal) {
+            const double target = fmax(out.rtol * out.res0[sys], floor_g);
+            const bool reached = !bad && rr <= target;
+            if (out.flags) {
+                int fl = out.flags[sys] & (4 | 8);   // keep the factorisation's zero-pivot / fallback bits
+                if (out.rtol > 0.0 && !reached) fl |= 1;
+                if (bad) fl |= 2;
+                out.flags[sys] = fl;
+            }
         }
         if (out.stats) {
             const double rout = re[I] * re[I];
@@ -479,7 +496,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
 // last zone: c R_{I+1/2}^2 W_k in the outermost zone, zero elsewhere (and zero everywhere
 // when there is no outgoing flux).
 __global__ __launch_bounds__(kBlock) void k_lum_seed(Shape sh, const double* __restrict__ r_edge,
-                                                     const Consts* __restrict__ cs, double* __restrict__ seed) {
+                                                     const Consts* __restrict__ cs, const double* add,
+                                                     double* seed) {
     const long long sys = blockIdx.x;
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
@@ -488,13 +506,43 @@ __global__ __launch_bounds__(kBlock) void k_lum_seed(Shape sh, const double* __r
     const size_t n = (size_t)I * N;
     for (size_t j = threadIdx.x; j < n; j += kBlock) {
         const int i = (int)(j / N), k = (int)(j % N);
-        seed[(size_t)sys * n + j] = (flux && i == I - 1) ? kCLight * ro * ro * cs->W[k] : 0.0;
+        const size_t c = (size_t)sys * n + j;
+        const double a = add ? add[c] : 0.0;
+        seed[c] = ((flux && i == I - 1) ? kCLight * ro * ro * cs->W[k] : 0.0) + a;
     }
 }
 
-hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, double* seed, hipStream_t st) {
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
+                           hipStream_t st) {
     const long long nsys = (long long)sh.S * sh.R;
-    hipLaunchKernelGGL(k_lum_seed, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, r_edge, cs, seed);
+    hipLaunchKernelGGL(k_lum_seed, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, r_edge, cs, add, seed);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- line-search backtrack
+
+__global__ __launch_bounds__(kBlock) void k_backtrack(Shape sh, double* __restrict__ psi, const double* __restrict__ dx,
+                                                      int* backtrack, double* alpha) {
+    const long long sys = blockIdx.x;
+    if (backtrack[sys] == 0) return;
+    const double a = alpha[sys];
+    const double coef = 0.5 * a - a;
+    const size_t n = (size_t)sh.I * sh.N;
+    for (size_t j = threadIdx.x; j < n; j += kBlock) {
+        const size_t cix = (size_t)sys * n + j;
+        psi[cix] = psi[cix] + __dmul_rn(coef, dx[cix]);      // trial moved back to alpha / 2
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        alpha[sys] = 0.5 * a;
+        backtrack[sys] = 0;
+    }
+}
+
+hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int* backtrack, double* alpha,
+                            hipStream_t st) {
+    const long long nsys = (long long)sh.S * sh.R;
+    hipLaunchKernelGGL(k_backtrack, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, psi, dx, backtrack, alpha);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_factor_solve.argtypes = [V, P(Inputs), V, V, V, I32]
     lib.tm_newton_step.argtypes = [V, P(Inputs), V, V, I32, D, P(Stats)]
     lib.tm_adjoint_step.argtypes = [V, P(Inputs), V, V, V, V, V, V, V, V]
-    lib.tm_luminosity_seed.argtypes = [V, P(Inputs), V]
+    lib.tm_luminosity_seed.argtypes = [V, P(Inputs), V, V]
     lib.tm_status_string.argtypes = [ctypes.c_int]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = [V]
@@ -242,11 +242,13 @@ class Context:
                                              _ptr(mu), _ptr(g_kappa_a), _ptr(g_eta), _ptr(g_kappa_s),
                                              _ptr(g_nes_amp)))
 
-    def luminosity_seed(self, f: DeviceFields, seed):
-        """dL_N/dpsi of the outer-boundary number luminosity into `seed` (cell array)."""
+    def luminosity_seed(self, f: DeviceFields, seed, add=None):
+        """seed = dL_N/dpsi (outer-boundary number luminosity) + add (cell arrays)."""
         self._cell(seed, "seed")
+        if add is not None:
+            self._cell(add, "add")
         inp = self._inputs(f)
-        self._check(self.lib.tm_luminosity_seed(self._h, ctypes.byref(inp), _ptr(seed)))
+        self._check(self.lib.tm_luminosity_seed(self._h, ctypes.byref(inp), _ptr(add), _ptr(seed)))
 
 
 # ---------------------------------------------------------------------- autograd

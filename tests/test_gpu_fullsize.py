@@ -1,0 +1,209 @@
+"""Full-size parity: the configurations at their real shapes, in the launch configuration the
+benchmark uses (all systems in one factor launch), checked against the oracle on sampled
+systems and through properties that hold for every system.  Also the multi-step
+checkpointed adjoint and the finite-difference check of the adjoint at the 1024-ray shape."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1809_05608_amd import multistep, tm
+
+pytestmark = pytest.mark.gpu
+TAU = 1e-30
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, ref):
+    return float(np.max(np.abs(a - ref) / np.maximum(np.abs(ref), TAU)))
+
+
+def _release():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _newton(wd, precision, max_iter, rtol):
+    ctx = tm.Context(tm.problem_of(wd, precision))
+    f = tm.DeviceFields.of(wd)
+    psi = wd.psi_n.clone()
+    st, stats = ctx.newton_step(f, wd.psi_n, psi, max_iter, rtol, raise_on_status=False)
+    torch.cuda.synchronize()
+    ctx.close()
+    return st, psi, stats
+
+
+def _oracle_systems(cfg, rays, systems, max_iter, rtol):
+    """Oracle results for (species, ray) pairs of the configuration, generated on the host."""
+    w = synth.make(cfg, rays=sorted(set(rays))).numpy()
+    idx = {r: j for j, r in enumerate(sorted(set(rays)))}
+    syss = oracle.systems_from_workload(w)
+    out = {}
+    for s, r in systems:
+        j = idx[r]
+        out[(s, r)] = oracle.newton(syss[s][j], w["psi_n"][s, j], max_iter=max_iter, rtol=rtol)
+    return out
+
+
+def test_cfg1_full_180_rays_fp64():
+    """180 rays x 540 zones x 20 groups x 4 species, FP64 Newton to 1e-10: sampled systems equal the
+    oracle (same iteration counts); every system converged, finite, and closes its number budget."""
+    say("case cfg1 full")
+    wd = synth.make(1, device="cuda")
+    st, psi, stats = _newton(wd, tm.PREC_FP64, 30, 1e-10)
+    assert st == 0, tm.STATUS_NAMES[st]
+    fl = stats["flags"].cpu().numpy()
+    assert not np.any(fl & (tm.FLAG_NOT_CONVERGED | tm.FLAG_NONFINITE | tm.FLAG_ZERO_PIVOT))
+    # budget identity: n - n_old + B - Q - NES = sum V W G, which is tiny at convergence
+    bud, ntot = stats["budget_n"].cpu().numpy(), stats["n_tot"].cpu().numpy()
+    assert np.all(np.abs(bud) <= 1e-8 * np.abs(ntot))
+    pairs = [(0, 0), (1, 61), (2, 122), (3, 179)]
+    ref = _oracle_systems(1, [r for _, r in pairs], pairs, 30, 1e-10)
+    P = psi.cpu().numpy()
+    it = stats["iters"].cpu().numpy().reshape(4, 180)
+    for (s, r), res in ref.items():
+        assert rel_err(P[s, r], res.psi) < 1e-12
+        assert it[s, r] == res.iters
+    _release()
+
+
+def test_cfg2_full_4096_rays_mixed_with_spikes():
+    """4096 rays x 540 x 20 x 4 with opacity spikes: the mixed path (FP32 factorisation) refined to
+    1e-12 agrees with the FP64 path on every cell to 1e-8, and with the oracle on sampled systems
+    including spike rays."""
+    say("case cfg2 full")
+    wd = synth.make(2, device="cuda")
+    st, pm, sm = _newton(wd, tm.PREC_MIXED, 30, 1e-12)
+    assert st == 0, tm.STATUS_NAMES[st]
+    st, pd, sd = _newton(wd, tm.PREC_FP64, 30, 1e-12)
+    assert st == 0, tm.STATUS_NAMES[st]
+    err = float(torch.max((pm - pd).abs() / pd.abs().clamp_min(TAU)).item())
+    assert err < 1e-8, err
+    ids, _, _ = synth.workload._spikes(2, 4096, 540)
+    pairs = [(0, int(ids[0])), (1, int(ids[1])), (3, 2048)]
+    ref = _oracle_systems(2, [r for _, r in pairs], pairs, 30, 1e-12)
+    P = pm.cpu().numpy()
+    for (s, r), res in ref.items():
+        assert rel_err(P[s, r], res.psi) < 1e-8
+    _release()
+
+
+def test_cfg4_full_16384_rays_bench_launch():
+    """The benchmark workload (16384 rays x 540 x 20 x 4, 65536 systems in one factor launch):
+    mixed and FP64 Newton on all systems, sampled systems against the oracle."""
+    say("case cfg4 full")
+    wd = synth.make(4, device="cuda")
+    st, pm, _ = _newton(wd, tm.PREC_MIXED, 30, 1e-12)
+    assert st == 0, tm.STATUS_NAMES[st]
+    st, pd, _ = _newton(wd, tm.PREC_FP64, 30, 1e-12)
+    assert st == 0, tm.STATUS_NAMES[st]
+    pairs = [(0, 0), (1, 5461), (2, 10922), (3, 16383)]
+    ref = _oracle_systems(4, [r for _, r in pairs], pairs, 30, 1e-12)
+    Pm, Pd = pm.cpu().numpy(), pd.cpu().numpy()
+    for (s, r), res in ref.items():
+        assert rel_err(Pd[s, r], res.psi) < 1e-12
+        assert rel_err(Pm[s, r], res.psi) < 1e-8
+    del wd, pm, pd
+    _release()
+
+
+def test_cfg3_adjoint_full_1024_rays():
+    """1024 rays x 540 x 20, FP64: adjoint of the outer luminosity against the oracle on rays 0-3,
+    and sum_j g_j theta_j v_j against central differences of J = sum L_N along 32 seeded random
+    directions over (kappa_a, eta, psi^n) (relative step 1e-4: J carries ~1e-11 rounding noise)."""
+    say("case cfg3 adjoint full")
+    wd = synth.make(3, device="cuda")
+    f = tm.DeviceFields.of(wd)
+    ctx = tm.Context(tm.problem_of(wd, tm.PREC_FP64))
+    iters = 8
+
+    def solve(fields, psi_n):
+        psi = psi_n.clone()
+        _, st = ctx.newton_step(fields, psi_n, psi, iters, 0.0)
+        return psi, st
+
+    psi, _ = solve(f, wd.psi_n)
+    seed = torch.empty_like(psi)
+    ctx.luminosity_seed(f, seed)
+    mu = torch.empty_like(psi)
+    g = {n: torch.empty_like(psi) for n in ("kappa_a", "eta", "kappa_s")}
+    gamp = torch.empty_like(wd.nes_amp)
+    ctx.adjoint_step(f, wd.psi_n, psi, seed, mu, g["kappa_a"], g["eta"], g["kappa_s"], gamp)
+    torch.cuda.synchronize()
+    # oracle on rays 0-3 (block-Thomas transpose; equal to the dense route by the oracle pins)
+    w4 = synth.make(3, rays=range(4)).numpy()
+    syss = oracle.systems_from_workload(w4)
+    P = psi.cpu().numpy()
+    for r in range(4):
+        ref = oracle.newton(syss[0][r], w4["psi_n"][0, r], max_iter=iters, rtol=0.0).psi
+        assert rel_err(P[0, r], ref) < 1e-12
+        A, bm, bp = oracle.jacobian_blocks(syss[0][r], ref)
+        sd = oracle.luminosity_seed(syss[0][r], ref.shape)
+        mo = oracle.block_thomas_solve(A, bm, bp, sd, transpose=True)
+        go = oracle.param_vjp(syss[0][r], ref, mo)
+        np.testing.assert_allclose(mu[0, r].cpu().numpy(), mo, rtol=1e-9, atol=1e-12 * np.max(np.abs(mo)))
+        for n in ("kappa_a", "eta", "kappa_s"):
+            np.testing.assert_allclose(g[n][0, r].cpu().numpy(), go[n], rtol=1e-8, atol=1e-11 * np.max(np.abs(go[n])))
+    # finite differences of J = sum over all systems of L_N along random directions
+    gen = torch.Generator(device="cpu").manual_seed(3001)
+    h = 1e-4
+    worst = 0.0
+    for d in range(32):
+        v = {n: torch.randn(tuple(psi.shape), generator=gen, dtype=torch.float64).to("cuda")
+             for n in ("kappa_a", "eta", "psi_n")}
+        an = float(sum((g[n] * getattr(wd, n) * v[n]).sum().item() for n in ("kappa_a", "eta")) +
+                   (mu * wd.psi_n * v["psi_n"]).sum().item())
+
+        def J(sign):
+            fk = tm.DeviceFields.of(wd, kappa_a=(wd.kappa_a * (1 + sign * h * v["kappa_a"])).contiguous(),
+                                    eta=(wd.eta * (1 + sign * h * v["eta"])).contiguous())
+            pn = (wd.psi_n * (1 + sign * h * v["psi_n"])).contiguous()
+            _, st = solve(fk, pn)
+            return float(st["lum_n"].sum().item())
+
+        fd = (J(+1) - J(-1)) / (2 * h)
+        worst = max(worst, abs(fd - an) / abs(an))
+    say("fd worst rel", worst)
+    assert worst < 1e-5
+    ctx.close()
+    _release()
+
+
+def test_multistep_checkpointed_adjoint_matches_oracle():
+    """Three drifting steps of the multi-step recipe (reduced shape): forward with one checkpoint per
+    step, reverse with regenerated inputs; dJ/dpsi^0 and per-step opacity gradients equal the
+    oracle's reverse recursion."""
+    say("case multistep")
+    steps, rays, zones, groups = 3, [3, 4], 24, 8
+    hosts = [synth.make(4, rays=rays, zones=zones, groups=groups, step=s) for s in range(steps)]
+    devs = [h.to("cuda") for h in hosts]
+    fields_at = lambda s: tm.DeviceFields.of(devs[s])          # noqa: E731
+    ctx = tm.Context(tm.problem_of(devs[0], tm.PREC_FP64))
+    psi0 = devs[0].psi_n
+    cps, _ = multistep.forward(ctx, fields_at, psi0, steps, max_iter=10, rtol=0.0)
+    grads = {}
+
+    def on_grad(s, mu, g):
+        grads[s] = g["kappa_a"].cpu().numpy()
+
+    d0 = multistep.adjoint(ctx, fields_at, psi0, cps, on_grad=on_grad).cpu().numpy()
+    W = [h.numpy() for h in hosts]
+    for sp in range(devs[0].S):
+        for r in range(len(rays)):
+            syss = [oracle.systems_from_workload(w)[sp][r] for w in W]
+            psis = oracle.multistep_forward(syss, W[0]["psi_n"][sp, r], max_iter=10, rtol=0.0)
+            for s in range(steps):
+                assert rel_err(cps[s][sp, r].cpu().numpy(), psis[s]) < 1e-12
+            g0, go = oracle.multistep_adjoint(syss, psis)
+            np.testing.assert_allclose(d0[sp, r], g0, rtol=1e-9, atol=1e-12 * np.max(np.abs(g0)))
+            for s in range(steps):
+                np.testing.assert_allclose(grads[s][sp, r], go[s]["kappa_a"], rtol=1e-8,
+                                           atol=1e-11 * np.max(np.abs(go[s]["kappa_a"])))
+    ctx.close()

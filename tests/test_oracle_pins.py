@@ -365,3 +365,37 @@ def test_pins_catch_transposed_nes_jacobian(monkeypatch):
     monkeypatch.setattr(ot, "jacobian_blocks", bad)
     with pytest.raises(AssertionError):
         test_jacobian_matches_central_differences(1)
+
+
+def test_multistep_adjoint_matches_central_differences():
+    """Three drifting steps, J = sum_s L(psi^s): the reverse recursion equals central differences of J
+    with respect to psi^0 and to the absorption opacity of the first and last step."""
+    ws = [synth.make(4, rays=[7], zones=8, groups=5, species=1, step=s).numpy() for s in range(3)]
+    syss = [oracle.systems_from_workload(w)[0][0] for w in ws]
+    syss = [dataclasses.replace(sy, kappa_a=sy.kappa_a * 1e3, eta=sy.eta * 1e3, kappa_s=sy.kappa_s * 1e3,
+                                nes_amp=sy.nes_amp * 1e4) for sy in syss]
+    psi0 = ws[0]["psi_n"][0, 0]
+
+    def fwd(sy_list, p0):
+        return oracle.multistep_forward(sy_list, p0, max_iter=10, rtol=0.0)
+
+    psis = fwd(syss, psi0)
+    g0, grads = oracle.multistep_adjoint(syss, psis)
+    rng = np.random.default_rng(21)
+    # J carries ~1e-11 relative rounding noise on this optically thick test system, so the
+    # step is 1e-4 relative (truncation O(h^2) ~ 1e-8) rather than a noise-dominated 1e-6
+    h = 1e-4
+
+    def J(sy_list, p0):
+        return oracle.multistep_objective(sy_list, fwd(sy_list, p0))
+
+    d = rng.standard_normal(psi0.shape) * psi0
+    fd = (J(syss, psi0 + h * d) - J(syss, psi0 - h * d)) / (2 * h)
+    assert abs(fd - np.sum(g0 * d)) <= 1e-5 * abs(fd)
+    for s in (0, 2):
+        d = rng.standard_normal(psi0.shape) * syss[s].kappa_a
+        plus = [dataclasses.replace(sy, kappa_a=sy.kappa_a + h * d) if j == s else sy for j, sy in enumerate(syss)]
+        minus = [dataclasses.replace(sy, kappa_a=sy.kappa_a - h * d) if j == s else sy for j, sy in enumerate(syss)]
+        fd = (J(plus, psi0) - J(minus, psi0)) / (2 * h)
+        an = np.sum(grads[s]["kappa_a"] * d)
+        assert abs(fd - an) <= 1e-5 * abs(an), (s, fd, an)

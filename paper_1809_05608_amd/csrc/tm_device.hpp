@@ -53,6 +53,15 @@ struct EdgeFlux {
     double H, dHu, dHv, dHlam;
 };
 
+// 1/x from the hardware estimate and two Newton steps (within an ulp of the IEEE quotient).
+__device__ __forceinline__ double drcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, double D,
                                               double floor, int limiter) {
     EdgeFlux f;
@@ -69,7 +78,7 @@ __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, do
     const double m = fmax(mean, floor);
     const double ad = fabs(delta);
     const double den = fma(3.0 * D, m, lam * ad);
-    const double inv = 1.0 / den;
+    const double inv = drcp(den);
     const double r = m * inv;             // m / den
     const double q = delta * inv;         // delta / den
     f.H = -lam * delta * r;

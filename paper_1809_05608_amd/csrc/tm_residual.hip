@@ -147,24 +147,40 @@ __device__ __forceinline__ int block_or(int v, double* sh) {
 
 // ---------------------------------------------------------------- residual / statistics
 
-// Mapping: one block per system.  The 256 threads cover ZB = 256/NT consecutive zones x NT
-// groups (thread = cell, so every global access is coalesced) and step through the system
-// in chunks of ZB zones.  Each chunk's psi rows and NES neighbour factors are staged in LDS
-// for the O(N) NES sums of a cell; the NES shape matrix is staged once per block.
-// Besides max|G| the kernel computes the rounding level of G (32 ulp of the largest sum of
-// term magnitudes in the system), below which the Newton stopping rule does not ask for
+// Mapping: one block per system.  The 256 threads form RZ = 256/NT rows of NT groups (thread =
+// cell, so every global access is coalesced); row r of a chunk holds zone z0 - 1 + r, and the
+// interior rows z0 .. z0 + RZ - 3 are the chunk's output zones, the first and last rows being
+// halo.  Per chunk: every cell brings psi and its transport opacity (one reciprocal for lambda)
+// to LDS, together with the chunk's zone edges, temperatures and NES amplitudes (one value per
+// thread); every edge flux is computed once, by the cell below the edge, into LDS; then each
+// output cell assembles G from the two edge fluxes of its zone, emission/absorption and the
+// O(N) NES sums over its zone's LDS row.  The loads of the next chunk are issued before the
+// current chunk is processed, so the memory latency overlaps the arithmetic (the barriers wait
+// for LDS traffic only).  The NES shape matrix is staged once per block.  Besides max|G| the
+// kernel computes the rounding level of G (32 ulp of the largest per-cell sum of term
+// magnitudes plus |psi| |dG/dpsi|), below which the Newton stopping rule does not ask for
 // further progress.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const Consts* __restrict__ cs,
                                                      const double* __restrict__ psi_n,
                                                      const double* __restrict__ psi, double* __restrict__ G_out,
                                                      double g_sign, ResidualOut out) {
-    constexpr int ZB = kBlock / NT;
+    constexpr int RZ = kBlock / NT;             // rows per chunk (zones incl. one halo on each side)
+    constexpr int ZB = RZ - 2;                  // output zones per chunk
     constexpr int PS = NT + 1;                  // padded LDS row stride (conflict-free column reads)
+    static_assert(3 * RZ + 2 <= kBlock, "one zone value per thread");
     __shared__ double s_P[NT * PS];
-    __shared__ double s_psi[ZB][PS];
-    __shared__ double s_d[ZB][PS];
+    __shared__ double s_psi[RZ][PS];
+    __shared__ double s_lam[RZ][PS];
+    __shared__ double s_d[RZ][PS];
+    __shared__ double s_H[RZ][PS];              // flux at the upper edge of the row's zone
+    __shared__ double s_du[RZ][PS];             // its derivative with respect to the lower zone
+    __shared__ double s_dv[RZ][PS];             // ... and to the upper zone
+    __shared__ double s_z[3 * RZ + 2];          // edges z0-1 .. z0+RZ, then T and amp of the rows
     __shared__ double red[kBlock / 64];
+    double* const s_re = s_z;
+    double* const s_T = s_z + RZ + 2;
+    double* const s_amp = s_z + 2 * RZ + 2;
     const long long sys = blockIdx.x;
     if (out.mode == kResTrial && out.pending[sys] == 0) return;         // no trial to evaluate
     const int I = sh.I, N = sh.N;
@@ -173,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
     const int t = threadIdx.x, zl = t / NT, k = t - zl * NT;
-    const bool tile = zl < ZB;
+    const bool tile = zl < RZ;
     const bool lane_ok = tile && k < N;
+    const bool out_row = zl >= 1 && zl <= RZ - 2;
 
     if (nes)
         for (int j = t; j < NT * NT; j += kBlock) s_P[(j / NT) * PS + (j % NT)] = cs->P[j / NT][j % NT];
@@ -185,63 +202,120 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     const double Wk = lane_ok ? cs->W[k] : 0.0;
     const double epsk = lane_ok ? cs->eps[k] : 0.0;
     const double dek = (lane_ok && k + 1 < N) ? cs->de[k] : 0.0;
+    const size_t sys_cell0 = (size_t)sys * I * N;
 
+    // per-thread inputs of one chunk: the cell's fields and one zone value
+    struct In {
+        double p, ka, et, ks, pn, zv;
+    };
+    // Every load is issued unconditionally from a clamped, in-bounds address and the value selected
+    // afterwards: straight-line code lets the wait for a chunk's data count exactly the loads
+    // issued after it, instead of draining the memory pipe.
+    auto load = [&](int z0, In& v) {
+        const int i = z0 - 1 + zl;
+        const bool in_zone = lane_ok && i >= 0 && i < I;
+        const bool outc = in_zone && out_row;
+        const size_t cb = sys_cell0 + (in_zone ? (size_t)i * N + k : 0);
+        const double lp = psi[cb], lka = f.kappa_a[cb], let = f.eta[cb], lks = f.kappa_s[cb], lpn = psi_n[cb];
+        const bool opac = diff ? in_zone : (emabs && outc);
+        v.p = (diff ? in_zone : outc) ? lp : 0.0;
+        v.ka = opac ? lka : 0.0;
+        v.et = opac ? let : 0.0;
+        v.ks = (diff && in_zone) ? lks : 0.0;
+        v.pn = outc ? lpn : 0.0;
+        const double* src = re;
+        bool zok = false;
+        double zdef = 0.0;
+        if (t < RZ + 2) {
+            const int j = z0 - 1 + t;
+            zok = j >= 0 && j <= I;
+            src = re + (zok ? j : 0);
+        } else if (t < 2 * RZ + 2) {
+            const int j = z0 - 1 + (t - RZ - 2);
+            zok = nes && j >= 0 && j < I;
+            src = zok ? f.temp + (size_t)ray * I + j : re;
+            zdef = 1.0;
+        } else if (t < 3 * RZ + 2) {
+            const int j = z0 - 1 + (t - 2 * RZ - 2);
+            zok = nes && j >= 0 && j < I;
+            src = zok ? f.nes_amp + (size_t)sys * I + j : re;
+        }
+        const double lz = *src;
+        v.zv = zok ? lz : zdef;
+    };
+
+    In cur;
+    load(0, cur);
     for (int z0 = 0; z0 < I; z0 += ZB) {
-        const int i = z0 + zl;
-        const bool ok = lane_ok && i < I;
-        const size_t cb = ((size_t)sys * I + (ok ? i : 0)) * N + (ok ? k : 0);
-        const double p = ok ? psi[cb] : 0.0;
+        In nxt;
+        load(z0 + ZB, nxt);                                 // in flight while this chunk is processed
+        const int i = z0 - 1 + zl;                          // this row's zone (may be a halo or outside)
+        const bool in_zone = lane_ok && i >= 0 && i < I;
+        const double p = cur.p;
+        const double lam = (diff && in_zone) ? drcp(cur.ka + cur.et + cur.ks) : 0.0;
         __syncthreads();                                    // previous chunk done with the LDS rows
         if (tile) {
-            s_psi[zl][k] = ok ? p : 0.0;
-            s_d[zl][k] = (nes && ok && k + 1 < N) ? exp(-dek / f.temp[(size_t)ray * I + i]) : 0.0;
+            s_psi[zl][k] = p;
+            s_lam[zl][k] = lam;
+        }
+        if (t < 3 * RZ + 2) s_z[t] = cur.zv;
+        __syncthreads();
+        if (tile) {
+            s_d[zl][k] = (nes && in_zone && out_row && k + 1 < N) ? exp(-dek * drcp(s_T[zl])) : 0.0;
+            // flux at the upper edge of this row's zone, computed once per edge
+            if (diff) {
+                double H = 0.0, du = 0.0, dv = 0.0;
+                if (in_zone && zl + 1 < RZ) {
+                    if (i + 1 < I) {
+                        const double rlo = s_re[zl], rhi = s_re[zl + 1], rp = s_re[zl + 2];
+                        const double D = 0.5 * (rhi + rp) - 0.5 * (rlo + rhi);
+                        const EdgeFlux e = edge_flux(p, s_psi[zl + 1][k], sqrt(lam * s_lam[zl + 1][k]), D,
+                                                     sh.psi_floor, sh.limiter);
+                        H = e.H;
+                        du = e.dHu;
+                        dv = e.dHv;
+                    } else if (sh.outer_bc == 1) {
+                        H = p;                              // free streaming, eq. a22 limit
+                        du = 1.0;
+                    }
+                }
+                s_H[zl][k] = H;                             // the edge below zone 0 has zero flux
+                s_du[zl][k] = du;
+                s_dv[zl][k] = dv;
+            }
         }
         __syncthreads();
-        if (!ok) continue;
+        const In now = cur;
+        cur = nxt;
+        if (!in_zone || !out_row) continue;
 
-        const double pn = psi_n[cb];
+        const size_t cb = sys_cell0 + (size_t)i * N + k;
+        const double pn = now.pn;
         double G = p - pn;
         double scale = fabs(p) + fabs(pn);
-        const double rlo = re[i], rhi = re[i + 1];
+        const double rlo = s_re[zl], rhi = s_re[zl + 1];
         const double V = shell_volume(rlo, rhi);
         double Hh = 0.0;
         double jd = 1.0;                                    // |dG_ik/dpsi_ik| bound, for the rounding level
         if (diff) {
-            const double A_lo = rlo * rlo, A_hi = rhi * rhi, rc = 0.5 * (rlo + rhi);
-            const double lam = inv_mfp(f, cb);
-            double Hlo = 0.0, dlo = 0.0, dhi = 0.0;
-            if (i > 0) {
-                const size_t cm = cb - N;
-                const double D_lo = rc - 0.5 * (re[i - 1] + rlo);
-                const EdgeFlux e = edge_flux(psi[cm], p, sqrt(lam * inv_mfp(f, cm)), D_lo, sh.psi_floor, sh.limiter);
-                Hlo = e.H;
-                dlo = e.dHv;
-            }
-            if (i + 1 < I) {
-                const size_t cp = cb + N;
-                const double D_hi = 0.5 * (rhi + re[i + 2]) - rc;
-                const EdgeFlux e = edge_flux(p, psi[cp], sqrt(lam * inv_mfp(f, cp)), D_hi, sh.psi_floor, sh.limiter);
-                Hh = e.H;
-                dhi = e.dHu;
-            } else if (sh.outer_bc == 1) {
-                Hh = p;                                     // free streaming, eq. a22 limit
-                dhi = 1.0;
-            }
-            G += c * (A_hi * Hh - A_lo * Hlo) / V;
-            scale += c * (fabs(A_hi * Hh) + fabs(A_lo * Hlo)) / V;
-            jd += c * (A_hi * fabs(dhi) + A_lo * fabs(dlo)) / V;
+            const double A_lo = rlo * rlo, A_hi = rhi * rhi;
+            const double Hlo = s_H[zl - 1][k], dlo = s_dv[zl - 1][k];
+            Hh = s_H[zl][k];
+            const double dhi = s_du[zl][k];
+            const double iV = drcp(V);
+            G += c * (A_hi * Hh - A_lo * Hlo) * iV;
+            scale += c * (fabs(A_hi * Hh) + fabs(A_lo * Hlo)) * iV;
+            jd += c * (A_hi * fabs(dhi) + A_lo * fabs(dlo)) * iV;
         }
-        double ka = 0.0, et = 0.0;
+        const double ka = now.ka, et = now.et;
         if (emabs) {
-            ka = f.kappa_a[cb];
-            et = f.eta[cb];
             G += c * (ka * p - et * (1.0 - p));
             scale += c * (fabs(ka * p) + fabs(et * (1.0 - p)));
             jd += c * (ka + et);
         }
         double S = 0.0;
         if (nes) {
-            const double amp = f.nes_amp[(size_t)sys * I + i];
+            const double amp = s_amp[zl];
             double sin_ = 0.0, sout = 0.0, e = 1.0;
             // k' > k: the out kernel carries exp(-(eps_k' - eps_k)/T) = prod_{j=k}^{k'-1} d_j
 #pragma unroll

@@ -166,7 +166,9 @@ tm_status tm_assemble(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
  * (TM_FLAG_PIVOT_FALLBACK).  The environment variable TM_PIVOT=always|never read at
  * tm_create forces partial pivoting or disables the fallback; TM_GROWTH_LIMIT sets
  * the guard (default 16).  rhs and x are cell arrays and may alias.  In TM_PREC_MIXED the
- * factorisation and solve run in float32 (x is the float32 solution widened).      */
+ * factorisation and solve run in float32 on the right-hand side divided by a power of two
+ * near its largest magnitude in the system (so residuals below the float32 range still
+ * solve); x is the float32 solution widened and scaled back.                         */
 tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
                           const double *rhs, double *x, int32_t transpose);
 

@@ -180,7 +180,7 @@ tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
 
 tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double rhs_sign,
                      double* x, double* psi_out, const int* active, bool fp32, bool transpose,
-                     double* dx = nullptr) {
+                     double* dx = nullptr, const double* rhs_max = nullptr) {
     long long batch = 0;
     TM_TRY(factor_batch(c, fp32, &batch));
     const int NT = tmk::padded_groups(c->p.n_groups);
@@ -192,6 +192,7 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     a.psi = psi;
     a.rhs = rhs;
     a.rhs_sign = rhs_sign;
+    a.rhs_max = fp32 ? rhs_max : nullptr;
     a.x = x;
     a.psi_out = psi_out;
     a.active = active;
@@ -352,7 +353,11 @@ tm_status tm_factor_solve(tm_ctx* c, const tm_inputs* in, const double* psi, con
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, c->p.n_groups, c->consts, c->stream),
                      "setup kernel"));
     TM_TRY(hip_check(c, hipMemsetAsync(c->flags, 0, n_systems(c->p) * sizeof(int), c->stream), "memset flags"));
-    return run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, c->p.precision == TM_PREC_MIXED, transpose != 0);
+    const bool fp32 = c->p.precision == TM_PREC_MIXED;
+    if (fp32)   // per-system max |rhs| for the power-of-two scaling of the float32 solve
+        TM_TRY(hip_check(c, tmk::launch_sys_absmax(rhs, n_systems(c->p), (long long)c->p.n_zones * c->p.n_groups,
+                                                   c->res, c->stream), "rhs scale kernel"));
+    return run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, fp32, transpose != 0, nullptr, fp32 ? c->res : nullptr);
 }
 
 tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, double* psi, int32_t max_iter,
@@ -402,7 +407,8 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
         TM_TRY(count_of(c->active, &nact));
         if (nact == 0) break;
         // Newton update psi += delta for the active systems (delta kept for backtracking)
-        TM_TRY(run_factor(c, in, psi, c->gbuf, -1.0, nullptr, psi, c->active, fp32, false, c->dbuf));
+        // res holds max |G| of the residual in gbuf for every active system (scaling of the float32 solve)
+        TM_TRY(run_factor(c, in, psi, c->gbuf, -1.0, nullptr, psi, c->active, fp32, false, c->dbuf, c->res));
         // line search on max|G| with the FP64 residual; a rejected trial is moved back to half the step
         o.mode = tmk::kResTrial;
         for (int t = 0; t < max_trials; ++t) {

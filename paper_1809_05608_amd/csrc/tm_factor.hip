@@ -46,6 +46,26 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return fma(r, e, r);
 }
 
+// Power-of-two scaling of a system's right-hand side for a float32 solve: the solve is linear, so
+// x = s solve(J, r / s) with s = 2^e near max|r| keeps right-hand sides (Newton residuals) below the
+// float32 range representable, and leaves every in-range float32 rounding unchanged.
+struct RhsScale {
+    double in, out;       // multiplier of the right-hand side, multiplier of the solution
+};
+template <typename T>
+__device__ __forceinline__ RhsScale rhs_scale(const FactorArgs& A, long long sys) {
+    RhsScale r{A.rhs_sign, 1.0};
+    if (sizeof(T) == 4 && A.rhs_max) {
+        const double m = A.rhs_max[sys];
+        if (m > 0.0 && m < INFINITY) {
+            const int e = ilogb(m);
+            r.in = ldexp(A.rhs_sign, -e);
+            r.out = ldexp(1.0, e);
+        }
+    }
+    return r;
+}
+
 // Max of a 32-bit key over each SL-lane group (SL = 16 or 32) of the wavefront.
 template <int SL>
 __device__ __forceinline__ uint32_t group_max(uint32_t v) {
@@ -146,10 +166,13 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     T ycar = (T)0;
     double psi_c = real ? psi[kk] : 0.0;
     double sig_c = real ? ka[kk] + et[kk] : 0.0;
-    double lam_c = real ? 1.0 / (sig_c + ks[kk]) : 1.0;
+    double lam_c = real ? rcp_nr(sig_c + ks[kk]) : 1.0;
     double dHu_lo = 0.0, dHv_lo = 0.0, bp_prev = 0.0;
     bool zp = false;
-    T growth = (T)0;                                  // largest |multiplier| (diagonal pivots)
+    // largest |multiplier| as a monotone key (diagonal pivots); for double the key is the upper word, so
+    // the guard compares magnitudes to about 2^-20 relative, ample for a growth threshold
+    uint32_t gkey = 0;
+    const RhsScale rsc = rhs_scale<T>(A, sys);
 
     for (int i = 0; i < I; ++i) {
         // lane index re-materialised per zone: comparisons with it are evaluated where used
@@ -162,10 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             const size_t cn = (size_t)(i + 1) * N + kk;
             psi_n1 = psi[cn];
             sig_n1 = ka[cn] + et[cn];
-            lam_n1 = 1.0 / (sig_n1 + ks[cn]);
+            lam_n1 = rcp_nr(sig_n1 + ks[cn]);
         }
         const double rlo = re[i], rhi = re[i + 1];
         const double V = shell_volume(rlo, rhi);
+        const double iV = rcp_nr(V);
         const double A_lo = rlo * rlo, A_hi = rhi * rhi;
         double dHu_hi = 0.0, dHv_hi = 0.0, V_hi = 1.0;
         if (i + 1 < I) {
@@ -182,10 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
         double diag = 1.0, bm = 0.0, bp = 0.0, bm_next = 0.0;
         if (diff) {
-            diag += c * (A_hi * dHu_hi - A_lo * dHv_lo) / V;
-            if (i + 1 < I) bp = c * A_hi * dHv_hi / V;
-            if (i > 0) bm = -c * A_lo * dHu_lo / V;
-            if (i + 1 < I) bm_next = -c * A_hi * dHu_hi / V_hi;
+            diag += c * (A_hi * dHu_hi - A_lo * dHv_lo) * iV;
+            if (i + 1 < I) bp = c * A_hi * dHv_hi * iV;
+            if (i > 0) bm = -c * A_lo * dHu_lo * iV;
+            if (i + 1 < I) bm_next = -c * A_hi * dHu_hi * rcp_nr(V_hi);
         }
         if (emabs) diag += c * sig_c;
 
@@ -209,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 // with M = that factor the NES entry is ca P (1 + w (M - 1)), w = psi_k above the diagonal
                 // and 1 - psi_k below it, and the diagonal sum is P (1 + v (M - 1)), v = 1 - psi_k' above
                 // and psi_k' below
-                const float sc = (float)(1.4426950408889634 / Tz);
+                const float sc = (float)(1.4426950408889634 * rcp_nr(Tz));
                 if (is_row) {
                     L.bc[k] = real ? (T)psi_c : (T)0;
                     L.dd[k] = (float)eps_k * sc;
@@ -273,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         if (!real) bm = bp = bm_next = 0.0;
 
         // ---- right-hand side (and, for the transpose, the transposed block plus its Schur update)
-        T g = real ? (T)(A.rhs_sign * rhs[(size_t)i * N + kk]) : (T)0;
+        T g = real ? (T)(rsc.in * rhs[(size_t)i * N + kk]) : (T)0;
         T bcoef;
         if constexpr (!TRANS) {
             g = fma(-(T)bm, ycar, g);
@@ -362,7 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 const T piv = L.prow[cc];
                 const T pinv = rcp_nr(piv);
                 const T f = isp ? (T)0 : ac * pinv;
-                growth = fmax(growth, fabs(f));
+                // the guard key and the own pivot are kept current in every step: left alone, the
+                // compiler defers both chains to the end of the zone and holds every step's values
+                gkey = max(gkey, abs_key_bits(f));
+                asm volatile("" : "+v"(gkey));
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
                     if (j != cc) a[j] = fma(-f, L.prow[j], a[j]);
@@ -370,6 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
                 const T bpiv = L.prow[NT + 1];
                 a[cc] = isp ? bpiv : -f * bpiv;
                 mypiv = isp ? piv : mypiv;
+                asm volatile("" : "+v"(mypiv));
                 wave_sync();
             }
             zp |= !(fabs(mypiv) > (T)0) || !isfinite(mypiv);
@@ -396,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     }
 
     // zero-pivot report and, for diagonal pivots, the growth guard (any lane of the system)
-    const bool lane_bad = is_row && (zp || !(growth <= (T)A.growth_limit));
+    const bool lane_bad = is_row && (zp || gkey > abs_key_bits((T)A.growth_limit));
     uint32_t any_bad;
     if constexpr (PIVOT) {
         any_bad = group_max<SL>(lane_bad ? 1u : 0u);
@@ -447,11 +475,12 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
         if (store_out) {
             const size_t ci = (size_t)i * N + k;
+            const double d = rsc.out * (double)dl;
             if (outp) {
-                outp[ci] += (double)dl;
-                if (dxp) dxp[ci] = (double)dl;
+                outp[ci] += d;
+                if (dxp) dxp[ci] = d;
             } else {
-                xp[ci] = (double)dl;
+                xp[ci] = d;
             }
         }
         dnext = dl;

@@ -46,6 +46,8 @@ struct FactorArgs {
     const double* psi;        // state at which J is evaluated [S][R][I][N]
     const double* rhs;        // right-hand side, cell array, multiplied by rhs_sign
     double rhs_sign;
+    const double* rhs_max;    // per system (global index): max |rhs|, for the float32 power-of-two
+                              // scaling of the right-hand side (nullable = no scaling)
     double* x;                // solution output (nullable when psi_out is set)
     double* psi_out;          // Newton: psi_out += delta (nullable)
     const int* active;        // per system (global index), nullable = all active
@@ -80,6 +82,7 @@ hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const 
 hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
                            hipStream_t st);
 
+hipError_t launch_sys_absmax(const double* v, long long nsys, long long per_sys, double* out, hipStream_t st);
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
 
 // psi += (alpha/2 - alpha) dx and alpha /= 2 for systems with backtrack set (which is cleared)

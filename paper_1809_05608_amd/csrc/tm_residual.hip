@@ -622,6 +622,23 @@ hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int*
 
 // ---------------------------------------------------------------- active-system count
 
+// max |v| over each system's cells (one block per system)
+__global__ __launch_bounds__(kBlock) void k_sys_absmax(const double* __restrict__ v, long long per_sys,
+                                                       double* __restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    const double* p = v + (size_t)blockIdx.x * per_sys;
+    double m = 0.0;
+    for (long long c = threadIdx.x; c < per_sys; c += kBlock) m = fmax(m, fabs(p[c]));
+    m = block_max(m, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
+
+hipError_t launch_sys_absmax(const double* v, long long nsys, long long per_sys, double* out, hipStream_t st) {
+    if (nsys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sys_absmax, dim3((unsigned)nsys), dim3(kBlock), 0, st, v, per_sys, out);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_count(const int* __restrict__ active, long long n, int* count) {
     __shared__ double red[kBlock / 64];
     double s = 0.0;

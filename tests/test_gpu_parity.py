@@ -323,3 +323,17 @@ def test_pivoting_policies_agree(monkeypatch, env, precision):
         assert np.all(fallback)
     else:
         assert not np.any(fallback)
+
+
+# ------------------------------------------------------------------ float32 range
+
+def test_mixed_precision_converges_below_float32_range():
+    """Occupations near 1e-200 (single zone and group): the float32 solve works on the residual
+    scaled by a power of two per system, so the mixed Newton step still reaches the oracle's answer."""
+    say("case mixed tiny occupations")
+    w = synth.make_custom(S=2, R=3, I=1, N=1)
+    assert float(np.max(w.psi_n.numpy())) < 1e-150
+    st, psi, stats = gpu_newton(w, 30, 1e-12, precision=tm.PREC_MIXED)
+    assert st == 0, tm.STATUS_NAMES[st]
+    ref, _ = oracle_newton(w, 30, 1e-12)
+    assert rel_err(psi, ref) < MIXED_BAR

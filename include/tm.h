@@ -143,7 +143,9 @@ tm_status tm_create(const tm_problem *problem, void *hip_stream, tm_ctx **out);
 tm_status tm_destroy(tm_ctx *ctx);
 
 /* Device bytes of workspace needed to factor `batch_systems` systems per launch
- * (0 means all S*R systems at once).  Returns 0 for an invalid problem.           */
+ * (0 means all S*R systems at once): (b + 15) slots of I*NT*(NT+1) values (NT = N
+ * padded to a multiple of 4; float32 in TM_PREC_MIXED, else double), the 15 spare
+ * slots filling a last partial wave group.  Returns 0 for an invalid problem.    */
 size_t tm_workspace_bytes(const tm_problem *problem, int64_t batch_systems);
 
 /* Hand the context caller-owned device workspace (>= tm_workspace_bytes(p, b) for

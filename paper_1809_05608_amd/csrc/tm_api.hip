@@ -162,8 +162,8 @@ tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
         size_t freeb = 0, totalb = 0;
         TM_TRY(hip_check(c, hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo"));
         long long b = ns;
-        while (b > 1 && (double)b * per > 0.7 * (double)freeb) b = (b + 1) / 2;
-        const size_t bytes = (size_t)b * per;
+        while (b > 1 && (double)(b + tmk::kWsPadSystems) * per > 0.7 * (double)freeb) b = (b + 1) / 2;
+        const size_t bytes = (size_t)(b + tmk::kWsPadSystems) * per;
         hipError_t e = hipMalloc(&c->ws, bytes);
         if (e != hipSuccess) {
             c->ws = nullptr;
@@ -172,7 +172,7 @@ tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
         c->ws_bytes = bytes;
         c->ws_owned = true;
     }
-    long long b = (long long)(c->ws_bytes / per);
+    long long b = (long long)(c->ws_bytes / per) - tmk::kWsPadSystems;
     if (b < 1) return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
     *batch = std::min(b, ns);
     return TM_OK;
@@ -204,7 +204,7 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     a.pending = psi_out ? c->pending : nullptr;
     a.alpha = psi_out ? c->alpha : nullptr;
     a.wsC = c->ws;
-    a.wsY = (char*)c->ws + (size_t)batch * c->p.n_zones * NT * NT * es;
+    a.wsY = (char*)c->ws + (size_t)(batch + tmk::kWsPadSystems) * c->p.n_zones * NT * NT * es;
     const long long ns = n_systems(c->p);
     const bool pivot_first = c->pivot_policy == 1;
     if (!pivot_first)
@@ -257,7 +257,8 @@ size_t tm_workspace_bytes(const tm_problem* p, int64_t batch_systems) {
     if (!valid_problem(p, nullptr) || batch_systems < 0) return 0;
     const long long ns = n_systems(*p);
     const long long b = batch_systems == 0 ? ns : std::min<long long>(batch_systems, ns);
-    return (size_t)b * tmk::factor_ws_bytes_per_system(p->n_zones, p->n_groups, p->precision == TM_PREC_MIXED);
+    return (size_t)(b + tmk::kWsPadSystems) *
+           tmk::factor_ws_bytes_per_system(p->n_zones, p->n_groups, p->precision == TM_PREC_MIXED);
 }
 
 tm_status tm_create(const tm_problem* p, void* stream, tm_ctx** out) {
@@ -313,7 +314,8 @@ tm_status tm_set_workspace(tm_ctx* c, void* dev, size_t bytes) {
     if (!c) return TM_ERR_INVALID_ARG;
     if ((dev == nullptr) != (bytes == 0))
         return set_err(c, TM_ERR_INVALID_ARG, "workspace pointer and size must both be set or both be 0");
-    if (dev && bytes < tmk::factor_ws_bytes_per_system(c->p.n_zones, c->p.n_groups, c->p.precision == TM_PREC_MIXED))
+    if (dev && bytes < (size_t)(1 + tmk::kWsPadSystems) * tmk::factor_ws_bytes_per_system(
+                           c->p.n_zones, c->p.n_groups, c->p.precision == TM_PREC_MIXED))
         return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
     if (c->ws && c->ws_owned) {
         (void)hipStreamSynchronize(c->stream);
@@ -396,6 +398,15 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
     o.iters = c->iters;
     o.max_iter = max_iter;
     o.rtol = rtol;
+    // conservation statistics are taken at every evaluated state, so the last evaluation of a system
+    // (its accepted state) leaves those of the returned psi
+    o.stats = stats != nullptr;
+    if (stats) {
+        o.n_tot = stats->n_tot;
+        o.e_tot = stats->e_tot;
+        o.budget = stats->budget_n;
+        o.lum = stats->lum_n;
+    }
     TM_TRY(hip_check(c, hipMemsetAsync(c->pending, 0, ns * sizeof(int), c->stream), "memset pending"));
     TM_TRY(hip_check(c, hipMemsetAsync(c->backtrack, 0, ns * sizeof(int), c->stream), "memset backtrack"));
     o.mode = tmk::kResInitial;
@@ -422,18 +433,8 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
         }
     }
 
-    // final flags and statistics at the returned psi
-    o.mode = tmk::kResFinal;
-    o.flags = c->flags;
-    o.stats = stats != nullptr;
-    if (stats) {
-        o.n_tot = stats->n_tot;
-        o.e_tot = stats->e_tot;
-        o.budget = stats->budget_n;
-        o.lum = stats->lum_n;
-    }
-    TM_TRY(hip_check(c, tmk::launch_residual(sh, f, c->consts, psi_n, psi, nullptr, 1.0, o, c->stream),
-                     "residual kernel"));
+    // final flags from the last evaluated residual of each system (its accepted state)
+    TM_TRY(hip_check(c, tmk::launch_final_flags(ns, c->res, c->tgt, rtol, c->flags, c->stream), "flags kernel"));
     if (stats) {
         auto cp = [&](void* dst, const void* src, size_t bytes) -> tm_status {
             if (!dst) return TM_OK;

@@ -151,8 +151,16 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     const double* az = (sh.terms & kNes) ? A.f.nes_amp + (size_t)sys * I : nullptr;
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
-    T* wsC = reinterpret_cast<T*>(A.wsC) + (size_t)sbc * I * NT * NT;
-    T* wsY = reinterpret_cast<T*>(A.wsY) + (size_t)sbc * I * NT;
+    // Workspace, interleaved by wave group: the SPW systems of group g keep, per zone i and column m,
+    // one run of SPW * NT values, system s at offset s * NT and row k at s * NT + k.  A wave's store or
+    // load of column m is then one contiguous run (3 * 20 floats at N = 20) rather than SPW separate
+    // pieces.  A last partial group has empty slots, which the workspace size allows for
+    // (kWsPadSystems); lanes of a clamped system use that system's slot.
+    const long long wg = sbc / SPW;
+    const int lo = (int)(sbc - wg * SPW) * NT + k;             // this lane's place in a run
+    constexpr int zs = SPW * NT;                                // values per (zone, column) run
+    T* wsC = reinterpret_cast<T*>(A.wsC) + (size_t)wg * SPW * I * NT * NT;
+    T* wsY = reinterpret_cast<T*>(A.wsY) + (size_t)wg * SPW * I * NT;
     const bool store = live && real;
 
     const T* Prow = s_P + kr * PS;                  // row k of the NES shape (zero outside N x N)
@@ -408,11 +416,11 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
 
         if (store) {
-            T* Cz = wsC + (size_t)i * NT * NT;
+            T* q = wsC + (size_t)i * NT * zs + lo;
 #pragma unroll
             for (int m = 0; m < NT; ++m)
-                if (m < N) Cz[m * NT + k] = a[m];
-            wsY[(size_t)i * NT + k] = ycar;
+                if (m < N) q[(size_t)m * zs] = a[m];
+            wsY[(size_t)i * zs + lo] = ycar;
         }
 
         psi_c = psi_n1;
@@ -452,18 +460,18 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
     T cr[NT], crn[NT];
     T yv = (T)0, yn = (T)0;
     {
-        const T* Cz = wsC + (size_t)(I - 1) * NT * NT;
+        const T* q = wsC + (size_t)(I - 1) * NT * zs + lo;
 #pragma unroll
-        for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? Cz[m * NT + k] : (T)0;
-        yv = real ? wsY[(size_t)(I - 1) * NT + k] : (T)0;
+        for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? q[(size_t)m * zs] : (T)0;
+        yv = real ? wsY[(size_t)(I - 1) * zs + lo] : (T)0;
     }
     T dnext = (T)0;
     for (int i = I - 1; i >= 0; --i) {
         if (i > 0) {
-            const T* Cz = wsC + (size_t)(i - 1) * NT * NT;
+            const T* q = wsC + (size_t)(i - 1) * NT * zs + lo;
 #pragma unroll
-            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? Cz[m * NT + k] : (T)0;
-            yn = real ? wsY[(size_t)(i - 1) * NT + k] : (T)0;
+            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? q[(size_t)m * zs] : (T)0;
+            yn = real ? wsY[(size_t)(i - 1) * zs + lo] : (T)0;
         }
         T dl = yv;
         if (i + 1 < I) {

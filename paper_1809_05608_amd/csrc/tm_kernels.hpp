@@ -14,7 +14,6 @@ enum ResidualMode : int {
     kResPlain = 0,      // max|G| only (tm_assemble)
     kResInitial = 1,    // first Newton pass: res0, accepted residual, target, activity
     kResTrial = 2,      // pending trials only: accept (stopping rule, activity) or ask to backtrack
-    kResFinal = 3,      // flags and conservation statistics at the returned state
 };
 
 // Inputs/outputs of the residual / statistics kernel, all per system of the launch.
@@ -29,8 +28,7 @@ struct ResidualOut {
     int* backtrack;     // set to 1 when the trial is rejected
     int* active;        // Newton activity flag
     const int* iters;   // updates applied so far
-    int* flags;         // TM_FLAG_* bits (final pass)
-    double* n_tot;      // statistics (final pass, nullable)
+    double* n_tot;      // conservation statistics of the evaluated state (nullable)
     double* e_tot;
     double* budget;
     double* lum;
@@ -82,6 +80,8 @@ hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const 
 hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
                            hipStream_t st);
 
+hipError_t launch_final_flags(long long n, const double* res, const double* tgt, double rtol, int* flags,
+                              hipStream_t st);
 hipError_t launch_sys_absmax(const double* v, long long nsys, long long per_sys, double* out, hipStream_t st);
 hipError_t launch_count_active(const int* active, long long n, int* count, hipStream_t st);
 
@@ -92,6 +92,9 @@ hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int*
 // active_out[j] = 1 where guard[j] != 0 (else 0); *count = number of such systems
 hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st);
 
+// Factor workspace: C and y per system slot; a batch of b systems takes b + kWsPadSystems slots (the
+// layout is interleaved by wave group of at most 16 systems, and a last partial group keeps empty slots).
+constexpr int kWsPadSystems = 15;
 size_t factor_ws_bytes_per_system(int I, int N, bool fp32);
 int padded_groups(int N);
 

@@ -401,15 +401,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
             } else {
                 out.backtrack[sys] = 1;
             }
-        } else if (out.mode == kResFinal) {
-            const double target = fmax(out.rtol * out.res0[sys], floor_g);
-            const bool reached = !bad && rr <= target;
-            if (out.flags) {
-                int fl = out.flags[sys] & (4 | 8);   // keep the factorisation's zero-pivot / fallback bits
-                if (out.rtol > 0.0 && !reached) fl |= 1;
-                if (bad) fl |= 2;
-                out.flags[sys] = fl;
-            }
         }
         if (out.stats) {
             const double rout = re[I] * re[I];
@@ -636,6 +627,29 @@ __global__ __launch_bounds__(kBlock) void k_sys_absmax(const double* __restrict_
 hipError_t launch_sys_absmax(const double* v, long long nsys, long long per_sys, double* out, hipStream_t st) {
     if (nsys <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sys_absmax, dim3((unsigned)nsys), dim3(kBlock), 0, st, v, per_sys, out);
+    return hipGetLastError();
+}
+
+// Final per-system flags of a Newton step from the last evaluated (accepted) residual: keeps the
+// factorisation's zero-pivot / fallback bits, sets 1 when rtol > 0 and max|G| is above its target,
+// 2 when the residual is not finite.
+__global__ __launch_bounds__(kBlock) void k_final_flags(long long n, const double* __restrict__ res,
+                                                        const double* __restrict__ tgt, double rtol,
+                                                        int* __restrict__ flags) {
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const double r = res[s];
+    int fl = flags[s] & (4 | 8);
+    if (!isfinite(r)) fl |= 2;
+    else if (rtol > 0.0 && !(r <= tgt[s])) fl |= 1;
+    flags[s] = fl;
+}
+
+hipError_t launch_final_flags(long long n, const double* res, const double* tgt, double rtol, int* flags,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_final_flags, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, res,
+                       tgt, rtol, flags);
     return hipGetLastError();
 }
 

@@ -337,3 +337,35 @@ def test_mixed_precision_converges_below_float32_range():
     assert st == 0, tm.STATUS_NAMES[st]
     ref, _ = oracle_newton(w, 30, 1e-12)
     assert rel_err(psi, ref) < MIXED_BAR
+
+
+# ------------------------------------------------------------------ caller workspace
+
+@pytest.mark.parametrize("precision", [tm.PREC_FP64, tm.PREC_MIXED])
+def test_caller_workspace_batches_equal_one_launch(precision):
+    """A caller workspace sized for 7 systems factors the 22 systems in batches of 7, 7, 7 and 1
+    (partial wave groups included): solves, transposed solves and the Newton step are bitwise those
+    of the self-allocated single launch."""
+    say("case caller workspace", precision)
+    w = synth.make_custom(S=2, R=11, I=23, N=20)
+    wd = w.to("cuda")
+    rng = np.random.default_rng(41)
+    psi = torch.as_tensor(w.psi_n.numpy() * 1.02, device="cuda")
+    rhs = torch.as_tensor(rng.standard_normal(tuple(psi.shape)), device="cuda")
+    out = []
+    for batch in (0, 7):
+        ctx, f = _ctx(wd, precision)
+        if batch:
+            ctx.set_workspace(ctx.workspace_bytes(batch))
+        x = torch.empty_like(psi)
+        xt = torch.empty_like(psi)
+        ctx.factor_solve(f, psi, rhs, x, False)
+        ctx.factor_solve(f, psi, rhs, xt, True)
+        pd = wd.psi_n.clone()
+        st, stats = ctx.newton_step(f, wd.psi_n, pd, 30, 1e-12, raise_on_status=False)
+        torch.cuda.synchronize()
+        assert st == 0
+        out.append((x.cpu().numpy(), xt.cpu().numpy(), pd.cpu().numpy(), stats["iters"].cpu().numpy()))
+        ctx.close()
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)

@@ -6,7 +6,9 @@ synthetic stellar-profile recipe of `synth`, generated directly in HBM.  One ben
 step = one implicit time step: the mixed-precision Newton iteration (FP32 block
 factorisation, FP64 residual/update/sums) refined to a 1e-12 relative residual.
 Alongside, the FP64 path is timed to the same tolerance (time-to-tolerance and the
-mixed-vs-FP64 error are reported), and the FP64 adjoint of the outer luminosity.
+mixed-vs-FP64 error are reported), the FP64 adjoint of the outer luminosity, and the
+configuration's multi-step job (10 drifting steps, then the adjoint over all of them with
+one checkpoint per step).
 
 Metric: Newton updates/s = sum over systems of (Newton updates applied) x I x N / time.
 Output: one JSON line on stdout (progress goes to stderr).
@@ -108,6 +110,83 @@ def time_kernel(torch, fn, reps):
     return sum(a.elapsed_time(b) for a, b in ev) / reps / 1e3
 
 
+def prealloc_workspace(torch, ctx):
+    """Hand the context its factor workspace before timing: all systems if they fit in 70% of the
+    free device memory, else the largest halving that does (the library then batches)."""
+    free = torch.cuda.mem_get_info()[0]
+    b = ctx.problem.n_species * ctx.problem.n_rays
+    while b > 1 and ctx.workspace_bytes(b) > 0.7 * free:
+        b = (b + 1) // 2
+    ctx.set_workspace(ctx.workspace_bytes(b))
+    return b
+
+
+def multistep_leg(tm, torch, synth, dev, rays, steps, rtol, max_iter):
+    """The configuration's multi-step job: `steps` consecutive implicit steps with drifting inputs
+    (mixed-precision Newton, one checkpoint per step), then the checkpointed FP64 adjoint of
+    J = sum_s L_N(psi^s) over all steps.  A step's drifted inputs are regenerated on the GPU when
+    needed (held one step at a time); that generation is excluded from the reported times."""
+    from paper_1809_05608_amd import multistep
+    gen = [0.0]
+    held = {}
+    marks = []                                   # (call start, call end) of each input generation
+
+    def fields_at(s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        marks.append([t0, t0])
+        held.clear()
+        ws = synth.make(4, rays=rays, step=s, device=dev)
+        held["w"] = ws
+        f = tm.DeviceFields.of(ws)
+        torch.cuda.synchronize()
+        marks[-1][1] = time.perf_counter()
+        gen[0] += marks[-1][1] - t0
+        return f
+
+    w0 = synth.make(4, rays=rays, step=0, device=dev)
+    psi0 = w0.psi_n.clone()
+    prob_m, prob_d = tm.problem_of(w0, tm.PREC_MIXED), tm.problem_of(w0, tm.PREC_FP64)
+    cells_per_sys = w0.I * w0.N
+    del w0
+    torch.cuda.empty_cache()
+    ctx = tm.Context(prob_m)
+    cps = [torch.empty_like(psi0) for _ in range(steps)]   # one checkpoint per step, allocated up front
+    prealloc_workspace(torch, ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats = multistep.forward(ctx, fields_at, psi0, steps, max_iter=max_iter, rtol=rtol, checkpoints=cps)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    t_fwd = t_end - t0 - gen[0]
+    per = [b[0] - a[1] for a, b in zip(marks, marks[1:] + [[t_end, t_end]])]
+    log("  forward steps (ms): " + " ".join(f"{1e3 * x:.0f}" for x in per))
+    marks.clear()
+    updates = sum(int(st["iters"].to(torch.int64).sum().item()) for st in stats) * cells_per_sys
+    iters = [float(st["iters"].double().mean()) for st in stats]
+    ctx.close()
+    torch.cuda.empty_cache()
+    log(f"  forward: {steps} steps in {1e3 * t_fwd:.0f} ms (generation {1e3 * gen[0]:.0f} ms excluded)")
+    gen[0] = 0.0
+    ctx = tm.Context(prob_d)
+    batch = prealloc_workspace(torch, ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d0 = multistep.adjoint(ctx, fields_at, psi0, cps)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0 - gen[0]
+    finite = bool(torch.isfinite(d0).all().item())
+    log(f"  adjoint: {steps} steps in {1e3 * t_adj:.0f} ms (generation {1e3 * gen[0]:.0f} ms excluded, "
+        f"factor batches of {batch} systems)")
+    ctx.close()
+    held.clear()
+    del cps, d0
+    torch.cuda.empty_cache()
+    return dict(steps=steps, forward_ms=1e3 * t_fwd, adjoint_ms=1e3 * t_adj,
+                forward_updates_per_s=updates / t_fwd, mean_iters_per_step=iters,
+                adjoint_precision="fp64", adjoint_factor_batch=batch, checkpoints=steps, gradient_finite=finite)
+
+
 def cpu_baseline(sample_systems: int, workers: int):
     """The FP64 oracle (as written, untuned) on a bounded sample of systems of the same workload."""
     import multiprocessing as mp
@@ -166,13 +245,15 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--multistep", type=int, default=10,
+                    help="steps of the multi-step leg (drifting inputs, checkpointed adjoint); 0 skips it")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short pass for rocprofv3: one mixed step, one launch of each timed kernel, "
                          "and a plain 1 GiB device copy that calibrates the HBM byte counters")
     a = ap.parse_args(argv)
     if a.profile_pass:
-        a.steps, a.warmup, a.kernel_reps, a.no_fp64, a.no_cpu = 1, 0, 1, True, True
+        a.steps, a.warmup, a.kernel_reps, a.no_fp64, a.no_cpu, a.multistep = 1, 0, 1, True, True, 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested); the transport systems of a "
               "multi-GPU run would be sharded by ray with no exchange inside a step", file=sys.stderr)
@@ -260,6 +341,14 @@ def main(argv=None):
                 alu_tflops=flops_launch / t_fac / 1e12, alu_peak_tflops=PEAK_VALU_TFLOPS,
                 roofline_ms=1e3 * max(t_hbm, t_alu), residual_kernel_ms=1e3 * t_res)
 
+    wmeta = dict(name=w.name, R=w.R, I=w.I, N=w.N, S=w.S)
+    multi = None
+    if a.multistep > 0:
+        log(f"multi-step leg: {a.multistep} drifting steps, then the checkpointed adjoint")
+        del psi_m, f, w
+        torch.cuda.empty_cache()
+        multi = multistep_leg(tm, torch, synth, dev, rays, a.multistep, a.rtol, a.max_iter)
+
     cpu = None
     if not a.no_cpu:
         log("CPU oracle baseline")
@@ -273,13 +362,15 @@ def main(argv=None):
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 factor + f64 residual", "data": "synthetic",
-        "config": {"workload": f"{w.name}: one implicit step, mixed precision Newton to rtol {a.rtol:g}",
-                   "rays": w.R, "zones": w.I, "groups": w.N, "species": w.S, "cells": cells,
+        "config": {"workload": f"{wmeta['name']}: one implicit step, mixed precision Newton to rtol {a.rtol:g}",
+                   "rays": wmeta["R"], "zones": wmeta["I"], "groups": wmeta["N"], "species": wmeta["S"],
+                   "cells": cells,
                    "mean_newton_iters": float(mixed_iters.mean())},
         "mixed_err_vs_fp64": err_mixed,
         "fp64": out_fp64,
         "mixed_vs_fp64_speedup": (out_fp64["ms_per_step"] / ms) if out_fp64 else None,
         "adjoint_fp64": out_adj,
+        "multistep": multi,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -10,6 +10,9 @@ Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
 `bench.py` may import this package.  It shares no code with the HIP path and
 must never be used as a fallback for it.
 
+The Y_e-coupled step (electron-fraction equation, eq. a62a, and the temperature update, eqs.
+a62b and a62d) is in `oracle.ye_coupled`.
+
 Parity status: every function below is pinned by `tests/test_oracle_pins.py`
 (closed forms, invariants, brute-force dense solves, finite differences);
 none is "parity unpinned".  The synthetic-workload recipe itself (module
@@ -21,3 +24,4 @@ from .transport import (  # noqa: F401
     newton, step_stats, luminosity, luminosity_seed, adjoint, param_vjp,
     newton_batch, residual_batch, multistep_forward, multistep_objective, multistep_adjoint,
 )
+from . import ye_coupled  # noqa: F401

@@ -239,6 +239,59 @@ def _build(name, cfg, S, R_full, I, N, rays, step, spikes, device, c_dt=C_LIGHT 
                     kappa_s=kappa_s, psi_n=psi_n, nes_amp=nes_amp, nes_g=nes_g)
 
 
+@dataclasses.dataclass
+class YeInputs:
+    """Extra inputs of the Y_e-coupled step for species 0 (nu_e) and 1 (anti-nu_e) of a workload.
+
+    rho [R][I] g/cm^3 and ye_n [R][I]; dka_dye, deta_dye [2][R][I][N] cm^-1 (derivatives of the
+    absorption and emission opacities of the two species with respect to Y_e); de_dT [R][I]
+    (MeV per baryon per MeV) and de_dye [R][I] (MeV per baryon), the matter's internal-energy
+    derivatives used by the post-solve temperature update.
+    """
+    rho: torch.Tensor
+    ye_n: torch.Tensor
+    dka_dye: torch.Tensor
+    deta_dye: torch.Tensor
+    de_dT: torch.Tensor
+    de_dye: torch.Tensor
+
+    def to(self, device):
+        return YeInputs(**{f.name: getattr(self, f.name).to(device) for f in dataclasses.fields(self)})
+
+    def numpy(self) -> dict:
+        return {f.name: getattr(self, f.name).detach().cpu().numpy() for f in dataclasses.fields(self)}
+
+
+def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0) -> YeInputs:
+    """Synthetic Y_e-coupling data for workload `w` (made by `make(cfg, rays=rays, step=step, ...)`).
+
+    * rho: the workload's own density profile (same seeds);
+    * Y_e^n(r) = 0.5 - 0.22 exp(-((log10 r - 6)/0.8)^2): 0.28 at the inner edge, 0.5 outside;
+    * absorption on free nucleons: kappa_a of nu_e scales with the neutron fraction 1 - Y_e and that
+      of anti-nu_e with the proton fraction Y_e, so dkappa_a/dY_e = -kappa_a/(1 - Y_e) and
+      +kappa_a/Y_e; the emissivities follow at fixed chemical potentials, deta/dY_e = eta (dkappa_a/dY_e)/kappa_a;
+    * de/dT = 1.5 + 0.5 T/MeV and de/dY_e = -10 T (MeV per baryon): smooth stand-ins for the EoS.
+    """
+    if w.S < 2:
+        raise ValueError("the Y_e coupling needs species 0 (nu_e) and 1 (anti-nu_e)")
+    R_full = CONFIGS[cfg]["R"]
+    if rays is None:
+        rays = range(R_full)
+    rays = np.asarray(rays, dtype=np.int64)
+    rho_np, _, _ = _profiles(cfg, R_full, w.I, rays, step)
+    dev = w.kappa_a.device
+    f64 = torch.float64
+    rho = torch.as_tensor(rho_np, dtype=f64, device=dev).contiguous()
+    rc = 0.5 * (w.r_edge[:, :-1] + w.r_edge[:, 1:])
+    ye_n = (0.5 - 0.22 * torch.exp(-((torch.log10(rc) - 6.0) / 0.8) ** 2)).contiguous()
+    frac = torch.stack([-1.0 / (1.0 - ye_n), 1.0 / ye_n])[:, :, :, None]        # [2][R][I][1]
+    dka = (frac * w.kappa_a[:2]).contiguous()
+    deta = (frac * w.eta[:2]).contiguous()
+    de_dT = (1.5 + 0.5 * w.temp).contiguous()
+    de_dye = (-10.0 * w.temp).contiguous()
+    return YeInputs(rho=rho, ye_n=ye_n, dka_dye=dka, deta_dye=deta, de_dT=de_dT, de_dye=de_dye)
+
+
 def make(cfg: int, *, rays: Optional[Sequence[int]] = None, zones: Optional[int] = None,
          groups: Optional[int] = None, species: Optional[int] = None, step: int = 0,
          device="cpu") -> Workload:

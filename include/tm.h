@@ -148,10 +148,12 @@ tm_status tm_destroy(tm_ctx *ctx);
  * slots filling a last partial wave group.  Returns 0 for an invalid problem.    */
 size_t tm_workspace_bytes(const tm_problem *problem, int64_t batch_systems);
 
-/* Hand the context caller-owned device workspace (>= tm_workspace_bytes(p, b) for
- * some batch b >= 1); the context then launches the factorisation in batches that
- * fit.  Without it, the context allocates workspace for all systems on first use.
- * Pass NULL/0 to go back to self-allocated workspace.                              */
+/* Hand the context caller-owned device workspace (>= tm_workspace_bytes(p, b) or
+ * tm_ye_workspace_bytes(p, b) for some batch b >= 1, else TM_ERR_WORKSPACE); the context
+ * then launches the factorisation in batches that fit.  A step whose own need for one
+ * batch exceeds the workspace returns TM_ERR_WORKSPACE.  Without it, the context
+ * allocates workspace for all systems on first use.  Pass NULL/0 to go back to
+ * self-allocated workspace.                                                          */
 tm_status tm_set_workspace(tm_ctx *ctx, void *device_ptr, size_t bytes);
 
 /* Residual G(psi) (eq. a58 times c dt) into `residual` (cell).  If `blocks` is not
@@ -206,6 +208,82 @@ tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
  * `add` (cell array) may be NULL or alias `seed`; a multi-step adjoint passes the adjoint of
  * the following step there.  Needs r_edge and e_edge only.                          */
 tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, const double *add, double *seed);
+
+/* ---------------------------------------------------------------------------------
+ * Y_e-coupled step (eq. a62a with the linearised system of eqs. a62ac-a62ae; matter
+ * energy and temperature of eqs. a62b, a62d).
+ *
+ * Electron neutrinos (species 0) and antineutrinos (species 1) of a ray exchange
+ * lepton number with the matter through emission and absorption, so Y_e of every zone
+ * is advanced implicitly with them:
+ *   G_Y,i = Y_e,i - Y_e,i^n + c dt zeta_i sum_k W_k (S_0,ik - S_1,ik),
+ *   zeta_i = 4 pi m_B / ((hc)^3 rho_i),  S_q = eta_q(Y_e) (1 - psi_q) - kappa_a,q(Y_e) psi_q,
+ * with m_B the atomic mass unit (1.66053906660e-24 g) and hc = 1.23984198e-10 MeV cm.
+ * Over the step the absorption and emission opacities of the pair are linear in Y_e,
+ * kappa_a,q(Y_e) = kappa_a,q + (Y_e - Y_e^n) dkappa_a,q/dY_e and likewise for eta; the
+ * species residuals use them in their emission/absorption term, while the transport mean
+ * free path (diffusion) stays at the opacities of Y_e^n.  NES does not depend on Y_e.
+ * The linearised system is block tridiagonal with (2N+1)-square diagonal blocks (psi of
+ * both species and Y_e of a zone) and diagonal off-diagonal blocks whose Y_e entries are
+ * zero; it is eliminated by block-Thomas with partial pivoting inside each block.
+ * Species 2..S-1 are independent of Y_e and are advanced by tm_newton_step on a problem
+ * of their own (their arrays are the tail of the cell, sysz arrays).
+ * --------------------------------------------------------------------------------- */
+
+typedef struct {
+    const double *rho;       /* zone [R][I], g cm^-3 (> 0)                                  */
+    const double *ye_n;      /* zone [R][I], Y_e at time level n                             */
+    const double *dka_dye;   /* [2][R][I][N] cm^-1: dkappa_a/dY_e of species 0 and 1; may be
+                                NULL when TM_TERM_EMABS is off                              */
+    const double *deta_dye;  /* [2][R][I][N] cm^-1: deta/dY_e; NULL as dka_dye              */
+} tm_ye_inputs;
+
+typedef struct {             /* every array is per ray [R], device memory                  */
+    double  *res_inf;        /* max |G| over both species and Y_e at the returned state      */
+    double  *res0_inf;       /* the same at the initial guess                                */
+    double  *lepton;         /* total lepton number of the ray divided by 4 pi:
+                                sum_i V_i [rho_i Y_e,i / m_B + (4 pi/(hc)^3) sum_k W_k
+                                (psi_0 - psi_1)] at the returned state (may be NULL)         */
+    int32_t *iters;          /* Newton updates applied                                      */
+    int32_t *flags;          /* TM_FLAG_* bits (TM_FLAG_ZERO_PIVOT: a zero pivot met)          */
+} tm_ye_stats;
+
+/* Device bytes of workspace needed to factor `batch_rays` coupled systems per launch
+ * (0 means all R): b slots of I*(2NT+1)^2 doubles (NT = N padded to a multiple of 4).
+ * Returns 0 for an invalid problem or N > 28.  A workspace given with
+ * tm_set_workspace serves both steps; the coupled step then runs in batches of
+ * floor(bytes / slot) rays.                                                          */
+size_t tm_ye_workspace_bytes(const tm_problem *problem, int64_t batch_rays);
+
+/* Backward-Euler Newton iteration for psi^{n+1} of species 0 and 1 together with
+ * Y_e^{n+1}, per ray.  Needs S >= 2, N <= 28 and TM_PREC_FP64 (the coupled elimination
+ * is FP64 only).  psi (cell array of the whole problem; only species 0 and 1 are read
+ * and written) and ye (zone [R][I]) hold the initial guess on entry, usually psi_n and
+ * ye_n, and the new state on return.  The stopping rule and line search are those of
+ * tm_newton_step applied to the coupled system: max|G| is over both species and Y_e,
+ * and the rounding level is the larger of the two species' levels and 32 * 2^-52 times
+ * the largest per-zone sum of the magnitudes of the terms of G_Y (emission and absorption
+ * counted separately) plus |Y_e| |dG_Y/dY_e|.  Synchronises the stream.  Returns as
+ * tm_newton_step; `stats` may be NULL.                                                */
+tm_status tm_ye_newton_step(tm_ctx *ctx, const tm_inputs *in, const tm_ye_inputs *yin,
+                            const double *psi_n, double *psi, double *ye, int32_t max_iter,
+                            double rtol, tm_ye_stats *stats);
+
+/* Matter energy change and temperature after the step, per zone:
+ *   de_i = -(4 pi/(hc)^3) (m_B/rho_i) sum_q w_q c dt sum_k eps_k W_k S_q,ik   (eq. a62b)
+ *   T_i^{n+1} = T_i^n + (de_i - (Y_e,i - Y_e,i^n) de/dY_e) / (de/dT)            (eq. a62d)
+ * de in MeV per baryon; S_q is the collision source of species q at psi (emission and
+ * absorption, with the opacities at ye for species 0 and 1, and NES; isoenergetic
+ * scattering exchanges no energy).  T^n is in->temp.  psi: cell array of all S species
+ * after the step; ye: zone, after the step.  stat_weights: HOST array of S statistical
+ * weights (e.g. 1, 1, 2, 2 when species 2 and 3 each stand for two flavours); S <= 16.
+ * de_dT (MeV per baryon per MeV) and de_dye (MeV per baryon): zone arrays of the
+ * matter's internal-energy derivatives.  de_out (zone) may be NULL; temp_out (zone) may
+ * alias in->temp (each zone reads its own T^n before writing).  Asynchronous.       */
+tm_status tm_temperature_update(tm_ctx *ctx, const tm_inputs *in, const tm_ye_inputs *yin,
+                                const double *psi, const double *ye, const double *stat_weights,
+                                const double *de_dT, const double *de_dye, double *de_out,
+                                double *temp_out);
 
 /* Human-readable name of a status code (static storage).                          */
 const char *tm_status_string(tm_status status);

@@ -181,7 +181,9 @@ def dense_jacobian(cs: CoupledSystem, u: np.ndarray) -> np.ndarray:
 
 def rounding_level(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> float:
     """Rounding level of G: the larger of the two species' levels (transport oracle definition)
-    and 32 ulp of the largest per-zone sum of |terms of G_Y| + |Y_e| |dG_Y/dY_e|."""
+    and 32 ulp of the largest per-zone sum of |terms of G_Y| + |Y_e| |dG_Y/dY_e|, where the terms of
+    the emission/absorption source count separately, |eta (1 - psi)| + |kappa_a psi|, as they do in
+    the species rows."""
     N = cs.N
     pe_n, pa_n, _ = unpack(u_n, N)
     pe, pa, ye = unpack(u, N)
@@ -192,9 +194,10 @@ def rounding_level(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> float:
     lev = max(residual_rounding_level(cs.nue, pe_n, pe), residual_rounding_level(cs.nuebar, pa_n, pa))
     mag = np.abs(ye) + np.abs(cs.ye_n)
     if cs.nue.terms & TERM_EMABS:
-        s_e = _ea_source(cs.nue, cs.dka_dye[0], cs.deta_dye[0], dy, pe)
-        s_a = _ea_source(cs.nuebar, cs.dka_dye[1], cs.deta_dye[1], dy, pa)
-        mag = mag + c * z * ((np.abs(s_e) + np.abs(s_a)) @ W)
+        for q, (sys, p) in enumerate(((cs.nue, pe), (cs.nuebar, pa))):
+            ka = sys.kappa_a + dy[:, None] * cs.dka_dye[q]
+            et = sys.eta + dy[:, None] * cs.deta_dye[q]
+            mag = mag + c * z * ((np.abs(et * (1.0 - p)) + np.abs(ka * p)) @ W)
     A, _, _ = jacobian_blocks(cs, u)
     mag = mag + np.abs(ye) * np.abs(A[:, 2 * N, 2 * N])
     return max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(mag)))

@@ -22,6 +22,7 @@ struct tm_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = false;
+    int ws_kind = 0;            // self-allocated for: 0 the single-species factor, 1 the coupled factor
     // small internal device buffers
     tmk::Consts* consts = nullptr;
     double* res = nullptr;      // [nsys]
@@ -45,6 +46,21 @@ struct tm_ctx {
     int pivot_policy = 0;
     double growth_limit = 16.0;
     long long pivot_fallbacks = 0;   // systems re-factored with partial pivoting since creation
+    // Y_e-coupled step, per ray [R] unless stated (allocated on first use)
+    double* y_res = nullptr;
+    double* y_res0 = nullptr;
+    double* y_res_acc = nullptr;
+    double* y_tgt = nullptr;
+    double* y_alpha = nullptr;
+    double* y_res_sp = nullptr;  // [2R] max|G| of the species part (written by the residual pass)
+    double* y_lev = nullptr;     // [2R] rounding level of the species part
+    double* y_gy = nullptr;      // [R][I] Y_e residual
+    double* y_dy = nullptr;      // [R][I] Y_e update
+    int* y_active = nullptr;
+    int* y_iters = nullptr;
+    int* y_flags = nullptr;
+    int* y_pending = nullptr;
+    int* y_backtrack = nullptr;
 };
 
 namespace {
@@ -157,6 +173,11 @@ tm_status ensure_gbuf(tm_ctx* c) {
 tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
     const size_t per = tmk::factor_ws_bytes_per_system(c->p.n_zones, c->p.n_groups, fp32);
     const long long ns = n_systems(c->p);
+    if (c->ws && c->ws_owned && c->ws_kind != 0) {     // sized for the coupled step: size it again
+        TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+        (void)hipFree(c->ws);
+        c->ws = nullptr;
+    }
     if (!c->ws) {
         // self-allocate: all systems if they fit in 70% of free memory, else the largest power-of-two share
         size_t freeb = 0, totalb = 0;
@@ -171,11 +192,82 @@ tm_status factor_batch(tm_ctx* c, bool fp32, long long* batch) {
         }
         c->ws_bytes = bytes;
         c->ws_owned = true;
+        c->ws_kind = 0;
     }
     long long b = (long long)(c->ws_bytes / per) - tmk::kWsPadSystems;
     if (b < 1) return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
     *batch = std::min(b, ns);
     return TM_OK;
+}
+
+tm_status ensure_ye(tm_ctx* c) {
+    if (c->y_res) return TM_OK;
+    const size_t R = c->p.n_rays, RI = (size_t)c->p.n_rays * c->p.n_zones;
+    auto dal = [&](double** p, size_t n, const char* what) { return hip_check(c, hipMalloc((void**)p, n * sizeof(double)), what); };
+    auto ial = [&](int** p, size_t n, const char* what) { return hip_check(c, hipMalloc((void**)p, n * sizeof(int)), what); };
+    TM_TRY(dal(&c->y_res, R, "hipMalloc y_res"));
+    TM_TRY(dal(&c->y_res0, R, "hipMalloc y_res0"));
+    TM_TRY(dal(&c->y_res_acc, R, "hipMalloc y_res_acc"));
+    TM_TRY(dal(&c->y_tgt, R, "hipMalloc y_tgt"));
+    TM_TRY(dal(&c->y_alpha, R, "hipMalloc y_alpha"));
+    TM_TRY(dal(&c->y_res_sp, 2 * R, "hipMalloc y_res_sp"));
+    TM_TRY(dal(&c->y_lev, 2 * R, "hipMalloc y_lev"));
+    TM_TRY(dal(&c->y_gy, RI, "hipMalloc y_gy"));
+    TM_TRY(dal(&c->y_dy, RI, "hipMalloc y_dy"));
+    TM_TRY(ial(&c->y_active, R, "hipMalloc y_active"));
+    TM_TRY(ial(&c->y_iters, R, "hipMalloc y_iters"));
+    TM_TRY(ial(&c->y_flags, R, "hipMalloc y_flags"));
+    TM_TRY(ial(&c->y_pending, R, "hipMalloc y_pending"));
+    TM_TRY(ial(&c->y_backtrack, R, "hipMalloc y_backtrack"));
+    return TM_OK;
+}
+
+// Rays per coupled factor launch that fit the workspace; allocates workspace for all rays if none.
+tm_status ye_batch(tm_ctx* c, long long* batch) {
+    const size_t per = tmk::ye_ws_bytes_per_ray(c->p.n_zones, c->p.n_groups);
+    const long long R = c->p.n_rays;
+    if (c->ws && c->ws_owned && c->ws_kind != 1) {     // sized for the single-species step: size it again
+        TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+        (void)hipFree(c->ws);
+        c->ws = nullptr;
+    }
+    if (!c->ws) {
+        size_t freeb = 0, totalb = 0;
+        TM_TRY(hip_check(c, hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo"));
+        long long b = R;
+        while (b > 1 && (double)b * per > 0.7 * (double)freeb) b = (b + 1) / 2;
+        hipError_t e = hipMalloc(&c->ws, (size_t)b * per);
+        if (e != hipSuccess) {
+            c->ws = nullptr;
+            return set_err(c, TM_ERR_WORKSPACE, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        c->ws_bytes = (size_t)b * per;
+        c->ws_owned = true;
+        c->ws_kind = 1;
+    }
+    const long long b = (long long)(c->ws_bytes / per);
+    if (b < 1) return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one ray's coupled factors");
+    *batch = std::min(b, R);
+    return TM_OK;
+}
+
+tm_status check_ye_inputs(tm_ctx* c, const tm_ye_inputs* y) {
+    if (!y) return set_err(c, TM_ERR_INVALID_ARG, "Y_e inputs are NULL");
+    if (!y->rho || !y->ye_n) return set_err(c, TM_ERR_INVALID_ARG, "rho and ye_n are required");
+    if ((c->p.terms & TM_TERM_EMABS) && (!y->dka_dye || !y->deta_dye))
+        return set_err(c, TM_ERR_INVALID_ARG, "dka_dye and deta_dye are required when TM_TERM_EMABS is on");
+    if (c->p.n_species < 2) return set_err(c, TM_ERR_INVALID_ARG, "the Y_e coupling needs species 0 and 1 (S >= 2)");
+    if (c->p.n_groups > tmk::kYeMaxGroups) return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step needs N <= 28");
+    return TM_OK;
+}
+
+tmk::YeFields ye_fields_of(const tm_ye_inputs& y) {
+    tmk::YeFields f;
+    f.rho = y.rho;
+    f.ye_n = y.ye_n;
+    f.dka = y.dka_dye;
+    f.deta = y.deta_dye;
+    return f;
 }
 
 tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double rhs_sign,
@@ -303,6 +395,13 @@ tm_status tm_destroy(tm_ctx* c) {
         (void)hipFree(c->pending);
         (void)hipFree(c->backtrack);
     }
+    if (c->y_res) {
+        (void)hipStreamSynchronize(c->stream);
+        for (double* p : {c->y_res, c->y_res0, c->y_res_acc, c->y_tgt, c->y_alpha, c->y_res_sp, c->y_lev, c->y_gy,
+                          c->y_dy})
+            (void)hipFree(p);
+        for (int* p : {c->y_active, c->y_iters, c->y_flags, c->y_pending, c->y_backtrack}) (void)hipFree(p);
+    }
     if (c->gbuf) (void)hipFree(c->gbuf);
     if (c->dbuf) (void)hipFree(c->dbuf);
     if (c->ws && c->ws_owned) (void)hipFree(c->ws);
@@ -314,9 +413,15 @@ tm_status tm_set_workspace(tm_ctx* c, void* dev, size_t bytes) {
     if (!c) return TM_ERR_INVALID_ARG;
     if ((dev == nullptr) != (bytes == 0))
         return set_err(c, TM_ERR_INVALID_ARG, "workspace pointer and size must both be set or both be 0");
-    if (dev && bytes < (size_t)(1 + tmk::kWsPadSystems) * tmk::factor_ws_bytes_per_system(
-                           c->p.n_zones, c->p.n_groups, c->p.precision == TM_PREC_MIXED))
-        return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one system's factors");
+    if (dev) {
+        // enough for one launch of either step (each step checks its own need when it runs)
+        const size_t one_sys = (size_t)(1 + tmk::kWsPadSystems) *
+                               tmk::factor_ws_bytes_per_system(c->p.n_zones, c->p.n_groups,
+                                                               c->p.precision == TM_PREC_MIXED);
+        const size_t one_ray = tmk::ye_ws_bytes_per_ray(c->p.n_zones, c->p.n_groups);
+        const size_t least = one_ray > 0 ? std::min(one_sys, one_ray) : one_sys;
+        if (bytes < least) return set_err(c, TM_ERR_WORKSPACE, "workspace smaller than one launch's factors");
+    }
     if (c->ws && c->ws_owned) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->ws);
@@ -475,6 +580,155 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
                                             c->stream),
                          "vjp kernel"));
     return TM_OK;
+}
+
+size_t tm_ye_workspace_bytes(const tm_problem* p, int64_t batch_rays) {
+    if (!valid_problem(p, nullptr) || batch_rays < 0) return 0;
+    const long long R = p->n_rays;
+    const long long b = batch_rays == 0 ? R : std::min<long long>(batch_rays, R);
+    return (size_t)b * tmk::ye_ws_bytes_per_ray(p->n_zones, p->n_groups);
+}
+
+tm_status tm_ye_newton_step(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* yin, const double* psi_n,
+                            double* psi, double* ye, int32_t max_iter, double rtol, tm_ye_stats* stats) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    TM_TRY(check_ye_inputs(c, yin));
+    if (c->p.precision != TM_PREC_FP64)
+        return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step is FP64 only (precision must be TM_PREC_FP64)");
+    if (!psi_n || !psi || !ye) return set_err(c, TM_ERR_INVALID_ARG, "psi_n, psi and ye are required");
+    if (max_iter < 0 || !(rtol >= 0.0)) return set_err(c, TM_ERR_INVALID_ARG, "max_iter >= 0 and rtol >= 0 required");
+    TM_TRY(ensure_small(c));
+    TM_TRY(ensure_gbuf(c));
+    TM_TRY(ensure_ye(c));
+    const long long R = c->p.n_rays;
+    const tmk::Shape sh = shape_of(c->p);
+    tmk::Shape sh2 = sh;                  // the species pair as a two-species problem (prefix of the arrays)
+    sh2.S = 2;
+    const tmk::Fields f = fields_of(*in);
+    const tmk::YeFields yf = ye_fields_of(*yin);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->y_iters, 0, R * sizeof(int), c->stream), "memset iters"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->y_flags, 0, R * sizeof(int), c->stream), "memset flags"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->y_pending, 0, R * sizeof(int), c->stream), "memset pending"));
+    TM_TRY(hip_check(c, hipMemsetAsync(c->y_backtrack, 0, R * sizeof(int), c->stream), "memset backtrack"));
+
+    auto count_of = [&](const int* arr, int* out_n) -> tm_status {
+        TM_TRY(hip_check(c, tmk::launch_count_active(arr, R, c->count, c->stream), "count kernel"));
+        TM_TRY(hip_check(c, hipMemcpyAsync(c->h_count, c->count, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                         "copy count"));
+        TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+        *out_n = *c->h_count;
+        return TM_OK;
+    };
+    tmk::ResidualOut o{};
+    o.mode = tmk::kResEval;
+    o.res = c->y_res_sp;
+    o.level = c->y_lev;
+    tmk::YeOut yo{};
+    yo.res = c->y_res;
+    yo.res0 = c->y_res0;
+    yo.res_acc = c->y_res_acc;
+    yo.tgt = c->y_tgt;
+    yo.alpha = c->y_alpha;
+    yo.pending = c->y_pending;
+    yo.backtrack = c->y_backtrack;
+    yo.active = c->y_active;
+    yo.iters = c->y_iters;
+    yo.lepton = stats ? stats->lepton : nullptr;      // taken at every evaluated state; the last is the returned one
+    yo.max_iter = max_iter;
+    yo.rtol = rtol;
+    auto evaluate = [&](int mode) -> tm_status {
+        o.pending = mode == tmk::kResInitial ? nullptr : c->y_pending;
+        yo.mode = mode;
+        TM_TRY(hip_check(c, tmk::launch_residual(sh2, f, c->consts, psi_n, psi, c->gbuf, 1.0, o, c->stream),
+                         "residual kernel"));
+        return hip_check(c, tmk::launch_ye_couple(sh, f, yf, c->consts, psi, ye, c->gbuf, c->y_gy, c->y_lev, yo,
+                                                  c->stream), "coupling kernel");
+    };
+    TM_TRY(evaluate(tmk::kResInitial));
+
+    long long batch = 0;
+    TM_TRY(ye_batch(c, &batch));
+    tmk::YeFactorArgs a;
+    a.sh = sh;
+    a.f = f;
+    a.y = yf;
+    a.cs = c->consts;
+    a.psi = psi;
+    a.ye = ye;
+    a.G = c->gbuf;
+    a.GY = c->y_gy;
+    a.rhs_sign = -1.0;
+    a.psi_out = psi;
+    a.ye_out = ye;
+    a.dx = c->dbuf;
+    a.dY = c->y_dy;
+    a.active = c->y_active;
+    a.flags = c->y_flags;
+    a.iters = c->y_iters;
+    a.pending = c->y_pending;
+    a.alpha = c->y_alpha;
+    a.ws = static_cast<double*>(c->ws);
+    const int max_trials = 9;                              // alpha = 1, 1/2, ..., 1/256
+    for (int it = 0; it < max_iter; ++it) {
+        int nact = 0;
+        TM_TRY(count_of(c->y_active, &nact));
+        if (nact == 0) break;
+        for (long long r0 = 0; r0 < R; r0 += batch) {
+            a.ray0 = r0;
+            a.nray = std::min(batch, R - r0);
+            TM_TRY(hip_check(c, tmk::launch_ye_factor(a, c->stream), "coupled factor kernel"));
+        }
+        for (int t = 0; t < max_trials; ++t) {
+            TM_TRY(evaluate(tmk::kResTrial));
+            int nback = 0;
+            TM_TRY(count_of(c->y_backtrack, &nback));
+            if (nback == 0) break;
+            TM_TRY(hip_check(c, tmk::launch_ye_backtrack(sh, psi, ye, c->dbuf, c->y_dy, c->y_backtrack, c->y_alpha,
+                                                         c->stream), "backtrack kernel"));
+        }
+    }
+    TM_TRY(hip_check(c, tmk::launch_final_flags(R, c->y_res, c->y_tgt, rtol, c->y_flags, c->stream), "flags kernel"));
+    if (stats) {
+        auto cp = [&](void* dst, const void* src, size_t bytes) -> tm_status {
+            if (!dst) return TM_OK;
+            return hip_check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "copy stats");
+        };
+        TM_TRY(cp(stats->res_inf, c->y_res, R * sizeof(double)));
+        TM_TRY(cp(stats->res0_inf, c->y_res0, R * sizeof(double)));
+        TM_TRY(cp(stats->iters, c->y_iters, R * sizeof(int)));
+        TM_TRY(cp(stats->flags, c->y_flags, R * sizeof(int)));
+    }
+    std::vector<int> fl(R);
+    TM_TRY(hip_check(c, hipMemcpyAsync(fl.data(), c->y_flags, R * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                     "copy flags"));
+    TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+    int any = 0;
+    for (int v : fl) any |= v;
+    if (any & TM_FLAG_NONFINITE) return set_err(c, TM_ERR_NONFINITE, "non-finite residual in some ray");
+    if (any & TM_FLAG_ZERO_PIVOT) return set_err(c, TM_ERR_SINGULAR, "zero pivot in some coupled block");
+    if (any & TM_FLAG_NOT_CONVERGED) return set_err(c, TM_ERR_NOT_CONVERGED, "some ray missed rtol");
+    c->err.clear();
+    return TM_OK;
+}
+
+tm_status tm_temperature_update(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* yin, const double* psi,
+                                const double* ye, const double* stat_weights, const double* de_dT,
+                                const double* de_dye, double* de_out, double* temp_out) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    TM_TRY(check_ye_inputs(c, yin));
+    if (!in->temp) return set_err(c, TM_ERR_INVALID_ARG, "temp (T^n) is required");
+    if (!psi || !ye || !stat_weights || !de_dT || !de_dye || !temp_out)
+        return set_err(c, TM_ERR_INVALID_ARG, "psi, ye, stat_weights, de_dT, de_dye and temp_out are required");
+    if (c->p.n_species > 16) return set_err(c, TM_ERR_INVALID_ARG, "the temperature update takes S <= 16");
+    TM_TRY(ensure_small(c));
+    const tmk::Shape sh = shape_of(c->p);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
+    return hip_check(c, tmk::launch_ye_temperature(sh, fields_of(*in), ye_fields_of(*yin), c->consts, psi, ye,
+                                                   stat_weights, de_dT, de_dye, de_out, temp_out, c->stream),
+                     "temperature kernel");
 }
 
 tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, double* seed) {

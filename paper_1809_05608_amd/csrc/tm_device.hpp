@@ -46,6 +46,12 @@ struct Fields {
 
 constexpr unsigned kDiffusion = 1u, kEmAbs = 2u, kNes = 4u;
 
+// Electron-fraction coupling (eq. a62a): zeta = 4 pi m_B / ((hc)^3 rho) turns sum_k W_k psi (MeV^3)
+// into neutrinos per baryon.  m_B is taken as the atomic mass unit; both constants are CODATA 2018.
+constexpr double kBaryonMassG = 1.66053906660e-24;    // g
+constexpr double kHcMeVCm = 1.23984198e-10;           // MeV cm
+constexpr double kFourPiOverHc3 = 4.0 * 3.14159265358979323846 / (kHcMeVCm * kHcMeVCm * kHcMeVCm);
+
 // Limited flux at an interior edge between zone values u (inner) and v (outer):
 //   H = -lam m (v - u) / (3 D m + lam |v - u|),  m = max((u + v)/2, floor)   (eqs. a59, a20)
 // and its partial derivatives with respect to u, v and lam.
@@ -88,6 +94,63 @@ __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, do
     f.dHv = 0.5 * dHm + dHd;
     f.dHlam = -3.0 * D * delta * r * r;
     return f;
+}
+
+// Monotone 32-bit key of |v| (sign dropped): for double, the upper word, which orders magnitudes to
+// about 2^-20 relative; for float, the whole word.
+__device__ __forceinline__ uint32_t abs_key_bits(double v) {
+    return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+}
+__device__ __forceinline__ uint32_t abs_key_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
+
+// Max of a 32-bit key over each SL-lane group (SL = 16 or 32) of the wavefront.
+template <int SL>
+__device__ __forceinline__ uint32_t group_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    if constexpr (SL == 32) {
+        auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);                   // rows 0<->1, 2<->3
+        v = max((uint32_t)sw[0], (uint32_t)sw[1]);
+    }
+    return v;
+}
+
+// Intra-wavefront ordering point for LDS exchange between lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block-wide deterministic reductions over kBlock threads (fixed shuffle + LDS order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < kBlock / 64; ++j) s += sh[j];
+    return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+    for (int j = 1; j < kBlock / 64; ++j) s = fmax(s, sh[j]);
+    return s;
+}
+
+__device__ __forceinline__ int block_or(int v, double* sh) {
+    return block_max(v ? 1.0 : 0.0, sh) > 0.0 ? 1 : 0;
 }
 
 // Zone geometry from three consecutive edges (lo = i-1/2, hi = i+1/2, hi2 = i+3/2):

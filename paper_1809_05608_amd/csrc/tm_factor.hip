@@ -23,11 +23,6 @@
 
 namespace tmk {
 
-__device__ __forceinline__ uint32_t abs_key_bits(double v) {
-    return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
-}
-__device__ __forceinline__ uint32_t abs_key_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
-
 __device__ __forceinline__ double texp(double x) { return exp(x); }
 __device__ __forceinline__ float texp(float x) { return __expf(x); }
 
@@ -64,27 +59,6 @@ __device__ __forceinline__ RhsScale rhs_scale(const FactorArgs& A, long long sys
         }
     }
     return r;
-}
-
-// Max of a 32-bit key over each SL-lane group (SL = 16 or 32) of the wavefront.
-template <int SL>
-__device__ __forceinline__ uint32_t group_max(uint32_t v) {
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
-    if constexpr (SL == 32) {
-        auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);                   // rows 0<->1, 2<->3
-        v = max((uint32_t)sw[0], (uint32_t)sw[1]);
-    }
-    return v;
-}
-
-// Intra-wavefront ordering point for LDS exchange between lanes.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T, int NT>

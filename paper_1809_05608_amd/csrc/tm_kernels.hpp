@@ -14,6 +14,8 @@ enum ResidualMode : int {
     kResPlain = 0,      // max|G| only (tm_assemble)
     kResInitial = 1,    // first Newton pass: res0, accepted residual, target, activity
     kResTrial = 2,      // pending trials only: accept (stopping rule, activity) or ask to backtrack
+    kResEval = 3,       // G, max|G| and the rounding level only; with `pending` set, only systems whose
+                        // ray (sys % R) has a pending trial (the species part of the Y_e-coupled step)
 };
 
 // Inputs/outputs of the residual / statistics kernel, all per system of the launch.
@@ -32,6 +34,7 @@ struct ResidualOut {
     double* e_tot;
     double* budget;
     double* lum;
+    double* level;      // rounding level of G of the evaluated state (nullable)
     int stats;
     int max_iter;
     double rtol;
@@ -91,6 +94,75 @@ hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int*
 
 // active_out[j] = 1 where guard[j] != 0 (else 0); *count = number of such systems
 hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st);
+
+// ---------------------------------------------------------------- Y_e-coupled step (eqs. a62a-a62ae)
+
+// Extra inputs of the coupled step, all device memory: zone arrays [R][I], and the Y_e derivatives of
+// the absorption and emission opacities of species 0 (nu_e) and 1 (anti-nu_e), [2][R][I][N].
+struct YeFields {
+    const double* rho;
+    const double* ye_n;
+    const double* dka;
+    const double* deta;
+};
+
+// Per-ray state of the coupled Newton iteration (the same quantities as ResidualOut, per ray).
+struct YeOut {
+    int mode;           // kResInitial or kResTrial
+    double* res;        // max |G| over both species and Y_e
+    double* res0;
+    double* res_acc;
+    double* tgt;
+    double* alpha;
+    int* pending;
+    int* backtrack;
+    int* active;
+    const int* iters;
+    double* lepton;     // total lepton number / (4 pi) of the evaluated state (nullable)
+    int max_iter;
+    double rtol;
+};
+
+struct YeFactorArgs {
+    Shape sh;                 // the problem (S >= 2; species 0 and 1 are the coupled pair)
+    Fields f;
+    YeFields y;
+    const Consts* cs;
+    const double* psi;        // iterate, cell array [S][R][I][N] (species 0, 1 read)
+    const double* ye;         // iterate [R][I]
+    const double* G;          // species residual [2][R][I][N] (right-hand side times rhs_sign)
+    const double* GY;         // Y_e residual [R][I]
+    double rhs_sign;
+    double* psi_out;          // psi += delta (species 0, 1)
+    double* ye_out;           // ye += delta_Y
+    double* dx;               // delta of the species cells [2][R][I][N]
+    double* dY;               // delta of Y_e [R][I]
+    const int* active;        // per ray, nullable = all
+    int* flags;               // per ray: zero-pivot bit
+    int* iters;               // per ray
+    int* pending;             // per ray
+    double* alpha;            // per ray
+    double* ws;               // per ray slot: I * (2 NT + 1) * (2 NT + 1) doubles
+    long long ray0;           // first ray of the batch
+    long long nray;           // rays in the batch
+};
+
+// Species residual G (from the single-species residual pass, opacities at Y_e^n) completed in place
+// with the Y_e terms, the Y_e residual GY, max|G| and the rounding level per ray, and the Newton
+// bookkeeping of `out`; level_sp holds the rounding levels of the 2R species systems.
+hipError_t launch_ye_couple(const Shape& sh, const Fields& f, const YeFields& y, const Consts* cs, const double* psi,
+                            const double* ye, double* G, double* GY, const double* level_sp, const YeOut& out,
+                            hipStream_t st);
+hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st);
+// psi (species 0, 1) and ye += (alpha/2 - alpha) delta, alpha /= 2, for rays with backtrack set (cleared)
+hipError_t launch_ye_backtrack(const Shape& sh, double* psi, double* ye, const double* dx, const double* dY,
+                               int* backtrack, double* alpha, hipStream_t st);
+// Matter energy change (eq. a62b) and temperature (eq. a62d) per zone after the step.
+hipError_t launch_ye_temperature(const Shape& sh, const Fields& f, const YeFields& y, const Consts* cs,
+                                 const double* psi, const double* ye, const double* weights, const double* de_dT,
+                                 const double* de_dye, double* de_out, double* temp_out, hipStream_t st);
+size_t ye_ws_bytes_per_ray(int I, int N);
+constexpr int kYeMaxGroups = 28;          // 2 NT + 1 rows of a coupled block fit one wavefront
 
 // Factor workspace: C and y per system slot; a batch of b systems takes b + kWsPadSystems slots (the
 // layout is interleaved by wave group of at most 16 systems, and a last partial group keeps empty slots).

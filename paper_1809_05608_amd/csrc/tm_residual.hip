@@ -116,35 +116,6 @@ __device__ __forceinline__ double inv_mfp(const Fields& f, size_t c) {
     return 1.0 / (f.kappa_a[c] + f.eta[c] + f.kappa_s[c]);
 }
 
-// Block-wide deterministic reductions (fixed shuffle + LDS order).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int j = 0; j < kBlock / 64; ++j) s += sh[j];
-    return s;
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double s = sh[0];
-    for (int j = 1; j < kBlock / 64; ++j) s = fmax(s, sh[j]);
-    return s;
-}
-
-__device__ __forceinline__ int block_or(int v, double* sh) {
-    return block_max(v ? 1.0 : 0.0, sh) > 0.0 ? 1 : 0;
-}
-
 // ---------------------------------------------------------------- residual / statistics
 
 // Mapping: one block per system.  The 256 threads form RZ = 256/NT rows of NT groups (thread =
@@ -183,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     double* const s_amp = s_z + 2 * RZ + 2;
     const long long sys = blockIdx.x;
     if (out.mode == kResTrial && out.pending[sys] == 0) return;         // no trial to evaluate
+    if (out.mode == kResEval && out.pending && out.pending[sys % sh.R] == 0) return;
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
     const double* re = f.r_edge + (size_t)ray * (I + 1);
@@ -374,6 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     if (threadIdx.x == 0) {
         const double rr = bad ? __builtin_nan("") : res;
         out.res[sys] = rr;
+        if (out.level) out.level[sys] = floor_g;
         const int it = out.iters ? out.iters[sys] : 0;
         if (out.mode == kResInitial) {
             // Newton stopping rule: max|G| <= target = max(rtol * max|G_0|, rounding level of G), or no

@@ -1,0 +1,596 @@
+// Y_e-coupled transport step: the electron-fraction equation (eq. a62a) solved together with the
+// electron neutrinos and antineutrinos of each ray (linearised system, eqs. a62ac-a62ae), and the
+// matter energy change and temperature after the step (eqs. a62b, a62d).
+//
+// Unknowns per zone: psi of nu_e (species 0) in rows [0, N), psi of anti-nu_e (species 1) in rows
+// [NT, NT + N), Y_e in row 2 NT (NT = N padded to a multiple of 4; padded rows are identity rows).
+// Y_e has no radial coupling, so the off-diagonal blocks stay diagonal with zero Y_e entries and the
+// diagonal blocks are (2 NT + 1)-square.  The transport mean free path stays at Y_e^n during the step;
+// the absorption and emission opacities of the pair are linear in Y_e over the step, with their
+// derivatives given as inputs.
+//
+//   k_ye_couple       one block per ray: completes the species residual (evaluated by the
+//                     single-species residual kernel with the opacities of Y_e^n) with the Y_e terms,
+//                     evaluates the Y_e residual, max|G|, the rounding level, the lepton number and the
+//                     Newton/line-search decisions.
+//   k_ye_factor       one wavefront per ray: lane r owns row r of the coupled block.  Per zone the row is
+//                     assembled in registers, the Schur complement with the previous factor row is
+//                     formed, and in-place Gauss-Jordan elimination with partial pivoting (pivot search
+//                     as a max over the wavefront, pivot row broadcast through LDS) produces
+//                     C_i = Ahat_i^{-1} diag(bp_i) and y_i; the backward sweep x_i = y_i - C_i x_{i+1}
+//                     applies the Newton update.
+//   k_ye_backtrack    line-search move-back of rejected trials.
+//   k_ye_temperature  one thread per zone: energy-weighted collision sources of every species, the
+//                     matter energy change and the new temperature.
+#include "tm_kernels.hpp"
+
+namespace tmk {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// zeta of eq. a62a at density rho: neutrinos per baryon per unit sum_k W_k psi
+__device__ __forceinline__ double ye_zeta(double rho) { return kFourPiOverHc3 * kBaryonMassG / rho; }
+
+// ---------------------------------------------------------------- residual completion and decisions
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFields y, const Consts* __restrict__ cs,
+                                                      const double* __restrict__ psi, const double* __restrict__ ye,
+                                                      double* __restrict__ G, double* __restrict__ GY,
+                                                      const double* __restrict__ level_sp, YeOut out) {
+    __shared__ double red[kBlock / 64];
+    const long long ray = blockIdx.x;
+    if (out.mode == kResTrial && out.pending[ray] == 0) return;          // no trial to evaluate
+    const int R = sh.R, I = sh.I, N = sh.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane < NT ? 0 : 1;
+    const int k = lane - q * NT;
+    const bool real = lane < 2 * NT && k < N;                            // species q, group k
+    const int kk = real ? k : 0;
+    const double sgn = q == 0 ? 1.0 : -1.0;                              // nu_e carries +1, anti-nu_e -1
+    const double Wk = real ? cs->W[kk] : 0.0;
+    const double c = sh.c_dt;
+    const bool emabs = sh.terms & kEmAbs;
+    const double* re = f.r_edge + (size_t)ray * (I + 1);
+    const size_t cell0 = ((size_t)(real ? q : 0) * R + ray) * I * N;
+    const size_t zb = (size_t)ray * I;
+
+    double gmax = 0.0, mag_max = 0.0, lep = 0.0;
+    int bad = 0;
+    for (int i = wave; i < I; i += kBlock / 64) {
+        const double Y = ye[zb + i], Yn = y.ye_n[zb + i];
+        const double dy = Y - Yn;
+        double sY = 0.0, sAbs = 0.0, sD = 0.0, sL = 0.0;
+        if (real) {
+            const size_t ci = cell0 + (size_t)i * N + kk;
+            const double p = psi[ci];
+            double g = G[ci];
+            if (emabs) {
+                const double dka = y.dka[ci], det = y.deta[ci];
+                g += c * dy * (dka * p - det * (1.0 - p));              // opacities at Y_e instead of Y_e^n
+                const double em = (f.eta[ci] + dy * det) * (1.0 - p);
+                const double ab = (f.kappa_a[ci] + dy * dka) * p;
+                sY = sgn * Wk * (em - ab);
+                sAbs = Wk * (fabs(em) + fabs(ab));
+                sD = sgn * Wk * (det * (1.0 - p) - dka * p);
+            }
+            G[ci] = g;
+            sL = sgn * Wk * p;
+            bad |= !isfinite(g);
+            gmax = fmax(gmax, fabs(g));
+        }
+        sY = wave_sum(sY);
+        sAbs = wave_sum(sAbs);
+        sD = wave_sum(sD);
+        sL = wave_sum(sL);
+        if (lane == 0) {
+            const double rho = y.rho[zb + i];
+            const double z = ye_zeta(rho);
+            double gy = dy, mag = fabs(Y) + fabs(Yn), ayy = 1.0;
+            if (emabs) {
+                gy += c * z * sY;                                        // eq. a62a times c dt
+                mag += c * z * sAbs;
+                ayy += c * z * sD;
+            }
+            mag += fabs(Y) * fabs(ayy);
+            GY[zb + i] = gy;
+            bad |= !isfinite(gy);
+            gmax = fmax(gmax, fabs(gy));
+            mag_max = fmax(mag_max, mag);
+            lep += shell_volume(re[i], re[i + 1]) * (rho * Y / kBaryonMassG + kFourPiOverHc3 * sL);
+        }
+    }
+    const double res = block_max(gmax, red);
+    const double mag = block_max(mag_max, red);
+    bad = block_or(bad, red);
+    if (out.lepton) lep = block_sum(lep, red);
+    if (threadIdx.x == 0) {
+        const double rr = bad ? __builtin_nan("") : res;
+        out.res[ray] = rr;
+        const double floor_g = fmax(fmax(level_sp[ray], level_sp[R + ray]), 32.0 * 2.220446049250313e-16 * mag);
+        const int it = out.iters ? out.iters[ray] : 0;
+        if (out.mode == kResInitial) {
+            const double target = fmax(out.rtol * rr, floor_g);
+            out.res0[ray] = rr;
+            out.res_acc[ray] = rr;
+            out.tgt[ray] = target;
+            const bool stop = out.rtol > 0.0 && !bad && rr <= target;
+            out.active[ray] = (!stop && !bad && it < out.max_iter && rr > 0.0) ? 1 : 0;
+        } else {
+            // same line search and stopping rule as the single-species step, on the whole coupled system
+            const double racc = out.res_acc[ray], a = out.alpha[ray];
+            const bool near = racc <= 1e3 * out.tgt[ray];
+            const bool accept = near || rr <= (1.0 - kArmijo * a) * racc || a <= kAlphaMin;
+            if (accept) {
+                const double target = fmax(out.rtol * out.res0[ray], floor_g);
+                out.pending[ray] = 0;
+                out.backtrack[ray] = 0;
+                out.res_acc[ray] = rr;
+                out.tgt[ray] = target;
+                const bool stop = out.rtol > 0.0 && !bad && (rr <= target || (rr <= 1e3 * target && rr > 0.5 * racc));
+                out.active[ray] = (!stop && !bad && it < out.max_iter && rr > 0.0) ? 1 : 0;
+            } else {
+                out.backtrack[ray] = 1;
+            }
+        }
+        if (out.lepton) out.lepton[ray] = lep;
+    }
+}
+
+// ---------------------------------------------------------------- coupled block-Thomas factor and solve
+
+template <int NT>
+struct alignas(16) YeLds {
+    static constexpr int MT = 2 * NT + 1;
+    double prow[MT + 3];       // pivot row: [0, MT) entries, MT right-hand side, MT+1 diagonal of B
+    double bc[2 * NT];         // psi of the zone (both species); x_{i+1} in the backward sweep
+    double dd[NT];             // NES neighbour factors exp(-(eps_{j+1} - eps_j)/T)
+    double yr[2 * NT];         // Y_e row entries, one per species row
+    double ys[2 * NT];         // species terms of dG_Y/dY_e
+    double fix[MT][MT + 1];    // row-ownership fix-up after pivoting
+    int sidx[64];              // elimination step at which lane r was the pivot row
+};
+
+template <int NT>
+constexpr int ye_waves_per_block() { return NT <= 20 ? 4 : 2; }
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
+    constexpr int MT = 2 * NT + 1;              // rows of a coupled block (<= 57)
+    constexpr int NC = 2 * NT;                  // columns of C that can be non-zero (Y_e has bp = 0)
+    constexpr int WPB = ye_waves_per_block<NT>();
+    constexpr int PS = NT + 2;
+    __shared__ YeLds<NT> lds_all[WPB];
+    __shared__ double s_P[NT * PS];
+    for (int j = threadIdx.x; j < NT * NT; j += blockDim.x) s_P[(j / NT) * PS + (j % NT)] = A.cs->P[j / NT][j % NT];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long rb = (long long)blockIdx.x * WPB + wave;           // ray within the batch
+    if (rb >= A.nray) return;                                          // whole wave (no block barrier follows)
+    const long long ray = A.ray0 + rb;
+    if (A.active && A.active[ray] == 0) return;
+
+    YeLds<NT>& L = lds_all[wave];
+    const Shape& sh = A.sh;
+    const int N = sh.N, I = sh.I, R = sh.R;
+    const bool is_row = lane < MT;
+    const bool isY = lane == NC;
+    const int q = lane < NT ? 0 : 1;
+    const int k = lane - q * NT;
+    const bool q0 = q == 0;
+    const bool real = lane < NC && k < N;        // a species row of a real energy group
+    const int kk = real ? k : 0;
+    const int kr = is_row ? lane : 0;
+    const double sgn = q0 ? 1.0 : -1.0;
+    const size_t cell0 = ((size_t)(real ? q : 0) * R + ray) * I * N;
+    const double* psi = A.psi + cell0;
+    const double* ka = A.f.kappa_a + cell0;
+    const double* et = A.f.eta + cell0;
+    const double* ks = A.f.kappa_s + cell0;
+    const double* dka = A.y.dka + cell0;
+    const double* det = A.y.deta + cell0;
+    const double* rhs = A.G + cell0;
+    const size_t zb = (size_t)ray * I;
+    const double* re = A.f.r_edge + (size_t)ray * (I + 1);
+    const double* tz = A.f.temp + zb;
+    const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+    const double* az = nes ? A.f.nes_amp + ((size_t)(real ? q : 0) * R + ray) * I : nullptr;
+    const double c = sh.c_dt;
+    const double Wk = real ? A.cs->W[kk] : 0.0;
+    const double* Prow = s_P + kk * PS;
+    double* ws = A.ws + (size_t)rb * I * (NC + 1) * MT;                // zone i: C [NC][MT], then y [MT]
+
+    // ---------------------------------------------------------------- forward sweep
+    double a[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a[m] = 0.0;
+    double ycar = 0.0;
+    double psi_c = real ? psi[kk] : 0.0;
+    double sig_c = real ? ka[kk] + et[kk] : 0.0;
+    double lam_c = real ? drcp(sig_c + ks[kk]) : 1.0;
+    double dHu_lo = 0.0, dHv_lo = 0.0;
+    bool zp = false;
+
+    for (int i = 0; i < I; ++i) {
+        double psi_n1 = 0.0, sig_n1 = 0.0, lam_n1 = 1.0;
+        if (i + 1 < I && real) {
+            const size_t cn = (size_t)(i + 1) * N + kk;
+            psi_n1 = psi[cn];
+            sig_n1 = ka[cn] + et[cn];
+            lam_n1 = drcp(sig_n1 + ks[cn]);
+        }
+        const double rlo = re[i], rhi = re[i + 1];
+        const double iV = drcp(shell_volume(rlo, rhi));
+        const double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double dHu_hi = 0.0, dHv_hi = 0.0;
+        if (i + 1 < I) {
+            const double D_hi = 0.5 * (rhi + re[i + 2]) - 0.5 * (rlo + rhi);
+            if (diff && real) {
+                const EdgeFlux e = edge_flux(psi_c, psi_n1, sqrt(lam_c * lam_n1), D_hi, sh.psi_floor, sh.limiter);
+                dHu_hi = e.dHu;
+                dHv_hi = e.dHv;
+            }
+        } else if (sh.outer_bc == 1) {
+            dHu_hi = 1.0;                                   // free streaming: H = psi of the last zone
+        }
+        double diag = 1.0, bm = 0.0, bp = 0.0;
+        if (diff) {
+            diag += c * (A_hi * dHu_hi - A_lo * dHv_lo) * iV;
+            if (i + 1 < I) bp = c * A_hi * dHv_hi * iV;
+            if (i > 0) bm = -c * A_lo * dHu_lo * iV;
+        }
+        if (emabs) diag += c * sig_c;
+        if (!real) bm = bp = 0.0;
+
+        // Y_e terms of the zone (eq. a62ad: Y_e column of the species rows; eq. a62a: the Y_e row)
+        const double dy = A.ye[zb + i] - A.y.ye_n[zb + i];
+        const double z = ye_zeta(A.y.rho[zb + i]);
+        double ycol = 0.0;
+        if (emabs && real) {
+            const double dk = dka[(size_t)i * N + kk], de = det[(size_t)i * N + kk];
+            diag += c * dy * (dk + de);
+            ycol = c * (dk * psi_c - de * (1.0 - psi_c));
+            if (lane < NC) {
+                L.yr[lane] = -sgn * c * z * Wk * (sig_c + dy * (dk + de));
+                L.ys[lane] = sgn * Wk * (de * (1.0 - psi_c) - dk * psi_c);
+            }
+        } else if (lane < NC) {
+            L.yr[lane] = 0.0;
+            L.ys[lane] = 0.0;
+        }
+        double amp = 0.0;
+        if (nes) {
+            amp = az[i];
+            const double Tz = tz[i];
+            if (lane < NC) L.bc[lane] = real ? psi_c : 0.0;
+            if (lane < NT) L.dd[lane] = (lane + 1 < N) ? exp(-A.cs->de[lane] / Tz) : 0.0;
+        }
+        wave_sync();
+
+        // ---- row of Ahat_i = A_i - diag(bm_i) C_{i-1}
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = real ? -bm * a[m] : 0.0;
+        if (nes && real) {
+            // NES part of the species block: -c dt [(1 - psi_k) K^in_{kk'} + psi_k K^out_{kk'}], placed in
+            // the columns of the lane's own species; its diagonal sums go to diag
+            const double ca = -c * amp;
+            const double cap = ca * psi_c, cam = ca * (1.0 - psi_c);
+            const double* pq = L.bc + (q0 ? 0 : NT);
+            double er = 1.0, so = 0.0, si = 0.0;
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) {
+                if (kp > 0) er = (kp > k) ? er * L.dd[kp - 1] : 1.0;
+                const double po = Prow[kp] * er;
+                so = fma(po, 1.0 - pq[kp], so);
+                const double v = cap * po;
+                a[kp] = q0 ? a[kp] + v : a[kp];
+                a[NT + kp] = q0 ? a[NT + kp] : a[NT + kp] + v;
+            }
+            double el = 1.0;
+#pragma unroll
+            for (int kp = NT - 1; kp >= 0; --kp) {
+                el = (kp < k) ? el * L.dd[kp] : 1.0;
+                const double pi = Prow[kp] * el;
+                si = fma(pi, pq[kp], si);
+                const double v = cam * pi;
+                a[kp] = q0 ? a[kp] + v : a[kp];
+                a[NT + kp] = q0 ? a[NT + kp] : a[NT + kp] + v;
+            }
+            diag += c * amp * (si + so);
+        }
+        if (real) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (m < NC) a[m] += (m == lane) ? diag : 0.0;
+                else a[m] += ycol;
+            }
+        } else if (isY) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NC; ++m) {
+                a[m] = L.yr[m];
+                s += L.ys[m];
+            }
+            a[NC] = emabs ? 1.0 + c * z * s : 1.0;
+        } else {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) a[m] = (m == lane) ? 1.0 : 0.0;    // padded identity row
+        }
+        double g = 0.0;
+        if (real) g = fma(-bm, ycar, A.rhs_sign * rhs[(size_t)i * N + kk]);
+        else if (isY) g = A.rhs_sign * A.GY[zb + i];
+        const double bcoef = bp;
+
+        // ---- in-place Gauss-Jordan on [Ahat | diag(bp) | g], partial pivoting over the wavefront
+        bool used = !is_row;
+        double mypiv = 1.0;
+        int mycol = 0;
+#pragma unroll
+        for (int cc = 0; cc < MT; ++cc) {
+            const double ac = a[cc];
+            const uint32_t key = used ? 0u : ((abs_key_bits(ac) & ~63u) | (uint32_t)(63 - lane));
+            uint32_t km = group_max<32>(key);
+            km = max((uint32_t)__builtin_amdgcn_readlane((int)km, 0), (uint32_t)__builtin_amdgcn_readlane((int)km, 32));
+            const int p = 63 - (int)(km & 63u);
+            const bool isp = lane == p;
+            if (isp) {
+#pragma unroll
+                for (int j = 0; j < MT; ++j) L.prow[j] = a[j];
+                L.prow[MT] = g;
+                L.prow[MT + 1] = bcoef;
+            }
+            wave_sync();
+            const double piv = L.prow[cc];
+            zp |= !(piv != 0.0);
+            const double pinv = drcp(piv);
+            const double fm = isp ? 0.0 : ac * pinv;
+#pragma unroll
+            for (int j = 0; j < MT; ++j)
+                if (j != cc) a[j] = fma(-fm, L.prow[j], a[j]);
+            g = fma(-fm, L.prow[MT], g);
+            const double bpiv = L.prow[MT + 1];
+            a[cc] = isp ? bpiv : -fm * bpiv;
+            if (isp) {
+                used = true;
+                mypiv = piv;
+                mycol = cc;
+            }
+            wave_sync();
+        }
+        // restore row ownership: the lane holding unknown mycol writes its scaled row; slot sidx[m] (the
+        // step at which lane m was the pivot) holds column m of C
+        if (is_row) {
+            const double ip = drcp(mypiv);
+#pragma unroll
+            for (int cc = 0; cc < MT; ++cc) L.fix[mycol][cc] = a[cc] * ip;
+            L.fix[mycol][MT] = g * ip;
+            L.sidx[lane] = mycol;
+        }
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = is_row ? L.fix[kr][L.sidx[m]] : 0.0;
+        ycar = is_row ? L.fix[kr][MT] : 0.0;
+        wave_sync();
+
+        if (is_row) {
+            double* wz = ws + (size_t)i * (NC + 1) * MT + lane;
+#pragma unroll
+            for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = a[m];
+            wz[(size_t)NC * MT] = ycar;
+        }
+
+        psi_c = psi_n1;
+        sig_c = sig_n1;
+        lam_c = lam_n1;
+        dHu_lo = dHu_hi;
+        dHv_lo = dHv_hi;
+    }
+
+    // ---------------------------------------------------------------- backward sweep
+    double cr[NC], crn[NC];
+    double yv = 0.0, yn = 0.0;
+    {
+        const double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + kr;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) cr[m] = is_row ? wz[(size_t)m * MT] : 0.0;
+        yv = is_row ? wz[(size_t)NC * MT] : 0.0;
+    }
+    double dnext = 0.0;
+    for (int i = I - 1; i >= 0; --i) {
+        if (i > 0) {
+            const double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + kr;
+#pragma unroll
+            for (int m = 0; m < NC; ++m) crn[m] = is_row ? wz[(size_t)m * MT] : 0.0;
+            yn = is_row ? wz[(size_t)NC * MT] : 0.0;
+        }
+        double dl = yv;
+        if (i + 1 < I) {
+            if (lane < NC) L.bc[lane] = dnext;
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < NC; ++m) dl = fma(-cr[m], L.bc[m], dl);
+            wave_sync();
+        }
+        if (real) {
+            const size_t ci = cell0 + (size_t)i * N + kk;
+            A.psi_out[ci] += dl;
+            A.dx[ci] = dl;
+        } else if (isY) {
+            A.ye_out[zb + i] += dl;
+            A.dY[zb + i] = dl;
+        }
+        dnext = dl;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) cr[m] = crn[m];
+        yv = yn;
+    }
+    if (lane == 0) {
+        if (zp && A.flags) A.flags[ray] |= 4;
+        A.iters[ray] += 1;
+        A.pending[ray] = 1;                    // trial psi + delta awaits the line search
+        A.alpha[ray] = 1.0;
+    }
+}
+
+size_t ye_ws_bytes_per_ray(int I, int N) {
+    const int NT = padded_groups(N);
+    if (NT < 0 || N > kYeMaxGroups) return 0;
+    const size_t MT = 2 * NT + 1;
+    return (size_t)I * MT * MT * sizeof(double);     // per zone: C [2 NT][MT] and y [MT]
+}
+
+// ---------------------------------------------------------------- line-search move-back
+
+__global__ __launch_bounds__(kBlock) void k_ye_backtrack(Shape sh, double* __restrict__ psi, double* __restrict__ ye,
+                                                         const double* __restrict__ dx, const double* __restrict__ dY,
+                                                         int* backtrack, double* alpha) {
+    const long long ray = blockIdx.x;
+    if (backtrack[ray] == 0) return;
+    const double a = alpha[ray];
+    const double coef = 0.5 * a - a;
+    const size_t n = (size_t)sh.I * sh.N;
+    for (int q = 0; q < 2; ++q) {
+        const size_t base = ((size_t)q * sh.R + ray) * n;
+        for (size_t j = threadIdx.x; j < n; j += kBlock) psi[base + j] = psi[base + j] + __dmul_rn(coef, dx[base + j]);
+    }
+    const size_t zb = (size_t)ray * sh.I;
+    for (int i = threadIdx.x; i < sh.I; i += kBlock) ye[zb + i] = ye[zb + i] + __dmul_rn(coef, dY[zb + i]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        alpha[ray] = 0.5 * a;
+        backtrack[ray] = 0;
+    }
+}
+
+// ---------------------------------------------------------------- matter energy and temperature
+
+struct SpeciesWeights {
+    double w[16];
+};
+
+// de_i = -(4 pi/(hc)^3) (m_B/rho_i) sum_q w_q c dt sum_k eps_k W_k S_qk   (eq. a62b, MeV per baryon)
+// T_i^{n+1} = T_i^n + (de_i - (Y_e^{n+1} - Y_e^n) de/dY_e) / (de/dT)      (eq. a62d)
+// S_qk is the collision source of species q at psi^{n+1}: emission/absorption (for species 0 and 1 with
+// the opacities at Y_e^{n+1}) and NES; isoenergetic scattering exchanges no energy.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_ye_temperature(Shape sh, Fields f, YeFields y, const Consts* __restrict__ cs,
+                                                           const double* __restrict__ psi, const double* __restrict__ ye,
+                                                           SpeciesWeights wts, const double* __restrict__ de_dT,
+                                                           const double* __restrict__ de_dye, double* __restrict__ de_out,
+                                                           double* __restrict__ temp_out) {
+    const long long idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long nz = (long long)sh.R * sh.I;
+    if (idx >= nz) return;
+    const int R = sh.R, I = sh.I, N = sh.N;
+    const long long ray = idx / I;
+    const int i = (int)(idx - ray * I);
+    const bool emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
+    const double T = f.temp[idx];
+    const double dy = ye[idx] - y.ye_n[idx];
+    double d[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) d[j] = (nes && j + 1 < N) ? exp(-cs->de[j] / T) : 0.0;
+    double src = 0.0;
+    for (int s = 0; s < sh.S; ++s) {
+        const size_t cz = (((size_t)s * R + ray) * I + i) * N;
+        double p[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) p[k] = k < N ? psi[cz + k] : 0.0;
+        const double amp = nes ? f.nes_amp[((size_t)s * R + ray) * I + i] : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (k >= N) break;
+            double sk = 0.0;
+            if (emabs) {
+                double kap = f.kappa_a[cz + k], eta = f.eta[cz + k];
+                if (s < 2) {
+                    kap += dy * y.dka[cz + k];
+                    eta += dy * y.deta[cz + k];
+                }
+                sk = eta * (1.0 - p[k]) - kap * p[k];
+            }
+            if (nes) {
+                double sin_ = 0.0, sout = 0.0, e = 1.0;
+#pragma unroll
+                for (int kp = k + 1; kp < NT; ++kp) {          // k' > k: out factor exp(-(eps_k' - eps_k)/T)
+                    if (kp >= N) break;
+                    e *= d[kp - 1];
+                    sout = fma(cs->P[k][kp] * e, 1.0 - p[kp], sout);
+                    sin_ = fma(cs->P[k][kp], p[kp], sin_);
+                }
+                e = 1.0;
+#pragma unroll
+                for (int kp = k - 1; kp >= 0; --kp) {          // k' < k: in factor exp(-(eps_k - eps_k')/T)
+                    e *= d[kp];
+                    sin_ = fma(cs->P[k][kp] * e, p[kp], sin_);
+                    sout = fma(cs->P[k][kp], 1.0 - p[kp], sout);
+                }
+                sk += amp * ((1.0 - p[k]) * sin_ - p[k] * sout);
+            }
+            acc = fma(cs->eps[k] * cs->W[k], sk, acc);
+        }
+        src = fma(wts.w[s], sh.c_dt * acc, src);
+    }
+    const double de = -kFourPiOverHc3 * kBaryonMassG / y.rho[idx] * src;
+    if (de_out) de_out[idx] = de;
+    temp_out[idx] = T + (de - dy * de_dye[idx]) / de_dT[idx];
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define TM_YE_DISPATCH(NTV, ...)                                        \
+    switch (NTV) {                                                      \
+        case 4: { constexpr int NT = 4; __VA_ARGS__; } break;           \
+        case 8: { constexpr int NT = 8; __VA_ARGS__; } break;           \
+        case 12: { constexpr int NT = 12; __VA_ARGS__; } break;         \
+        case 16: { constexpr int NT = 16; __VA_ARGS__; } break;         \
+        case 20: { constexpr int NT = 20; __VA_ARGS__; } break;         \
+        case 24: { constexpr int NT = 24; __VA_ARGS__; } break;         \
+        case 28: { constexpr int NT = 28; __VA_ARGS__; } break;         \
+        default: return hipErrorInvalidValue;                           \
+    }
+
+hipError_t launch_ye_couple(const Shape& sh, const Fields& f, const YeFields& y, const Consts* cs, const double* psi,
+                            const double* ye, double* G, double* GY, const double* level_sp, const YeOut& out,
+                            hipStream_t st) {
+    TM_YE_DISPATCH(padded_groups(sh.N),
+                   hipLaunchKernelGGL(k_ye_couple<NT>, dim3((unsigned)sh.R), dim3(kBlock), 0, st, sh, f, y, cs, psi, ye,
+                                      G, GY, level_sp, out))
+    return hipGetLastError();
+}
+
+hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
+    TM_YE_DISPATCH(padded_groups(a.sh.N),
+                   constexpr int WPB = ye_waves_per_block<NT>();
+                   const long long blocks = (a.nray + WPB - 1) / WPB;
+                   hipLaunchKernelGGL(k_ye_factor<NT>, dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a))
+    return hipGetLastError();
+}
+
+hipError_t launch_ye_backtrack(const Shape& sh, double* psi, double* ye, const double* dx, const double* dY,
+                               int* backtrack, double* alpha, hipStream_t st) {
+    hipLaunchKernelGGL(k_ye_backtrack, dim3((unsigned)sh.R), dim3(kBlock), 0, st, sh, psi, ye, dx, dY, backtrack, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_ye_temperature(const Shape& sh, const Fields& f, const YeFields& y, const Consts* cs,
+                                 const double* psi, const double* ye, const double* weights, const double* de_dT,
+                                 const double* de_dye, double* de_out, double* temp_out, hipStream_t st) {
+    if (sh.S > 16) return hipErrorInvalidValue;
+    SpeciesWeights w{};
+    for (int s = 0; s < sh.S; ++s) w.w[s] = weights[s];
+    const long long nz = (long long)sh.R * sh.I;
+    const unsigned blocks = (unsigned)((nz + kBlock - 1) / kBlock);
+    TM_YE_DISPATCH(padded_groups(sh.N),
+                   hipLaunchKernelGGL(k_ye_temperature<NT>, dim3(blocks), dim3(kBlock), 0, st, sh, f, y, cs, psi, ye, w,
+                                      de_dT, de_dye, de_out, temp_out))
+    return hipGetLastError();
+}
+
+}  // namespace tmk

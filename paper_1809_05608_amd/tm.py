@@ -26,8 +26,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_ZERO_PIVOT, FLAG_PIVOT_FALLBACK = 1, 2, 4, 8
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
-            "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_status_string",
-            "tm_last_error"]
+            "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_workspace_bytes",
+            "tm_ye_newton_step", "tm_temperature_update", "tm_status_string", "tm_last_error"]
 
 
 class TMError(RuntimeError):
@@ -53,6 +53,14 @@ class Stats(ctypes.Structure):
                 ("res_inf", "res0_inf", "n_tot", "e_tot", "budget_n", "lum_n", "iters", "flags")]
 
 
+class YeInputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("rho", "ye_n", "dka_dye", "deta_dye")]
+
+
+class YeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("res_inf", "res0_inf", "lepton", "iters", "flags")]
+
+
 _lib = None
 
 
@@ -75,12 +83,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_newton_step.argtypes = [V, P(Inputs), V, V, I32, D, P(Stats)]
     lib.tm_adjoint_step.argtypes = [V, P(Inputs), V, V, V, V, V, V, V, V]
     lib.tm_luminosity_seed.argtypes = [V, P(Inputs), V, V]
+    lib.tm_ye_workspace_bytes.argtypes = [P(Problem), ctypes.c_int64]
+    lib.tm_ye_workspace_bytes.restype = ctypes.c_size_t
+    lib.tm_ye_newton_step.argtypes = [V, P(Inputs), P(YeInputs), V, V, V, I32, D, P(YeStats)]
+    lib.tm_temperature_update.argtypes = [V, P(Inputs), P(YeInputs), V, V, P(D), V, V, V, V]
     lib.tm_status_string.argtypes = [ctypes.c_int]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = [V]
     lib.tm_last_error.restype = ctypes.c_char_p
     for name in ("tm_create", "tm_destroy", "tm_set_workspace", "tm_assemble", "tm_factor_solve",
-                 "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed"):
+                 "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_newton_step",
+                 "tm_temperature_update"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -241,6 +254,66 @@ class Context:
         self._check(self.lib.tm_adjoint_step(self._h, ctypes.byref(inp), _ptr(psi_n), _ptr(psi_np1), _ptr(seed),
                                              _ptr(mu), _ptr(g_kappa_a), _ptr(g_eta), _ptr(g_kappa_s),
                                              _ptr(g_nes_amp)))
+
+    # ------------------------------------------------------------------ Y_e-coupled step
+    def _zone(self, t: torch.Tensor, name: str):
+        p = self.problem
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if tuple(t.shape) != (p.n_rays, p.n_zones):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {(p.n_rays, p.n_zones)}")
+        return t
+
+    def _ye_inputs(self, y) -> YeInputs:
+        """y: an object with rho, ye_n [R][I] and dka_dye, deta_dye [2][R][I][N] device tensors."""
+        p = self.problem
+        self._zone(y.rho, "rho"), self._zone(y.ye_n, "ye_n")
+        pair = (2, p.n_rays, p.n_zones, p.n_groups)
+        for name in ("dka_dye", "deta_dye"):
+            t = getattr(y, name)
+            if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != pair:
+                raise ValueError(f"{name} must be a contiguous float64 tensor of shape {pair} on {self.device}")
+        self._keep_ye = y
+        return YeInputs(*[_ptr(getattr(y, n)) for n in ("rho", "ye_n", "dka_dye", "deta_dye")])
+
+    def ye_workspace_bytes(self, batch_rays: int = 0) -> int:
+        return int(self.lib.tm_ye_workspace_bytes(ctypes.byref(self.problem), batch_rays))
+
+    def ye_newton_step(self, f: DeviceFields, y, psi_n, psi, ye, max_iter: int, rtol: float, with_stats=True,
+                       raise_on_status=True):
+        """Coupled Newton iteration for species 0, 1 and Y_e, in place on psi and ye; returns (status, stats)."""
+        self._cell(psi_n, "psi_n"), self._cell(psi, "psi"), self._zone(ye, "ye")
+        inp, yin = self._inputs(f), self._ye_inputs(y)
+        R = self.problem.n_rays
+        stats = None
+        st_struct = None
+        if with_stats:
+            d = dict(device=self.device)
+            stats = {n: torch.empty(R, dtype=torch.float64, **d) for n in ("res_inf", "res0_inf", "lepton")}
+            stats.update({n: torch.empty(R, dtype=torch.int32, **d) for n in ("iters", "flags")})
+            st_struct = YeStats(*[_ptr(stats[n]) for n in ("res_inf", "res0_inf", "lepton", "iters", "flags")])
+        st = self.lib.tm_ye_newton_step(self._h, ctypes.byref(inp), ctypes.byref(yin), _ptr(psi_n), _ptr(psi),
+                                        _ptr(ye), int(max_iter), float(rtol),
+                                        ctypes.byref(st_struct) if st_struct is not None else None)
+        if raise_on_status and st != TM_OK:
+            self._check(st)
+        return st, stats
+
+    def temperature_update(self, f: DeviceFields, y, psi, ye, stat_weights, de_dT, de_dye, temp_out, de_out=None):
+        """Matter energy change and temperature after the step (zone arrays temp_out, de_out)."""
+        self._cell(psi, "psi"), self._zone(ye, "ye"), self._zone(de_dT, "de_dT"), self._zone(de_dye, "de_dye")
+        self._zone(temp_out, "temp_out")
+        if de_out is not None:
+            self._zone(de_out, "de_out")
+        S = self.problem.n_species
+        if len(stat_weights) != S:
+            raise ValueError(f"stat_weights needs {S} values")
+        w = (ctypes.c_double * S)(*[float(v) for v in stat_weights])
+        inp, yin = self._inputs(f), self._ye_inputs(y)
+        self._check(self.lib.tm_temperature_update(self._h, ctypes.byref(inp), ctypes.byref(yin), _ptr(psi), _ptr(ye),
+                                                   w, _ptr(de_dT), _ptr(de_dye), _ptr(de_out), _ptr(temp_out)))
 
     def luminosity_seed(self, f: DeviceFields, seed, add=None):
         """seed = dL_N/dpsi (outer-boundary number luminosity) + add (cell arrays)."""

@@ -262,8 +262,10 @@ class YeInputs:
         return {f.name: getattr(self, f.name).detach().cpu().numpy() for f in dataclasses.fields(self)}
 
 
-def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0) -> YeInputs:
-    """Synthetic Y_e-coupling data for workload `w` (made by `make(cfg, rays=rays, step=step, ...)`).
+def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0,
+              R_full: Optional[int] = None) -> YeInputs:
+    """Synthetic Y_e-coupling data for workload `w` (made by `make(cfg, rays=rays, step=step, ...)`,
+    or by `make_custom(seed_cfg=cfg, R=R_full, ...)` with `R_full` given).
 
     * rho: the workload's own density profile (same seeds);
     * Y_e^n(r) = 0.5 - 0.22 exp(-((log10 r - 6)/0.8)^2): 0.28 at the inner edge, 0.5 outside;
@@ -274,7 +276,8 @@ def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step:
     """
     if w.S < 2:
         raise ValueError("the Y_e coupling needs species 0 (nu_e) and 1 (anti-nu_e)")
-    R_full = CONFIGS[cfg]["R"]
+    if R_full is None:
+        R_full = CONFIGS[cfg]["R"]
     if rays is None:
         rays = range(R_full)
     rays = np.asarray(rays, dtype=np.int64)

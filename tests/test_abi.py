@@ -33,7 +33,8 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"tm_problem": tm.Problem, "tm_inputs": tm.Inputs, "tm_stats": tm.Stats}
+    structs = {"tm_problem": tm.Problem, "tm_inputs": tm.Inputs, "tm_stats": tm.Stats,
+               "tm_ye_inputs": tm.YeInputs, "tm_ye_stats": tm.YeStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -93,3 +94,22 @@ def test_null_context_is_an_error():
     lib = tm.load_library()
     assert lib.tm_destroy(None) == 1
     assert lib.tm_last_error(None).decode() == "context is NULL"
+
+
+def test_ye_workspace_bytes_formula():
+    """The coupled step keeps, per ray and zone, C [2NT][2NT+1] and y [2NT+1] in float64."""
+    lib = tm.load_library()
+    p = _prob(S=4, R=10, I=540, N=20)
+    per = 540 * 41 * 41 * 8
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(p), 0) == 10 * per
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(p), 3) == 3 * per
+    p13 = _prob(S=2, R=10, I=7, N=13)                  # padded to 16 groups: blocks of 33
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(p13), 1) == 7 * 33 * 33 * 8
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(_prob(N=29)), 0) == 0     # 2 NT + 1 rows exceed a wavefront
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(p), -1) == 0
+
+
+def test_ye_entry_points_reject_a_null_context():
+    lib = tm.load_library()
+    assert lib.tm_ye_newton_step(None, None, None, None, None, None, 1, 0.0, None) == 1
+    assert lib.tm_temperature_update(None, None, None, None, None, None, None, None, None, None) == 1

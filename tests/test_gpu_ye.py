@@ -1,0 +1,260 @@
+"""Parity of the Y_e-coupled step of the HIP path (through the C ABI) with the FP64 CPU oracle
+(`oracle.ye_coupled`): the coupled Newton iteration, its residual norm and lepton number, the
+temperature update, batching over a caller workspace, and argument checks.
+
+Metric for psi: the difference relative to the largest occupation of the same zone and species,
+max_k |psi| (floored at tau).  The coupled block is eliminated with partial pivoting, so rounding
+enters every cell of a zone at the scale of that zone's largest entries; cells 30 decades below
+it (the high-energy tail of cold zones) carry that absolute rounding, not a relative one.  Two
+FP64 oracle routes (the 2N+1 block against the N blocks in the decoupled limit) differ by about
+1e-31 under this metric.  Y_e is compared relative to its largest value.  Bar: 1e-12 (FP64).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import ye_coupled as yc
+from paper_1809_05608_amd import tm
+
+pytestmark = pytest.mark.gpu
+TAU = 1e-30
+BAR = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def zone_err(a, ref):
+    """max |a - ref| / max(max_k |ref|, tau), over zones of every ray (arrays [R][I][N])."""
+    scale = np.maximum(np.max(np.abs(ref), axis=-1, keepdims=True), TAU)
+    return float(np.max(np.abs(a - ref) / scale))
+
+
+def _case(S=2, R=3, I=12, N=8, **kw):
+    w = synth.make_custom(S=S, R=R, I=I, N=N, **kw)
+    y = synth.ye_inputs(w, 0, R_full=R)
+    return w, y
+
+
+def _gpu(w, y, max_iter, rtol, psi0=None, ye0=None, raise_on_status=False):
+    wd, yd = w.to("cuda"), y.to("cuda")
+    ctx = tm.Context(tm.problem_of(wd))
+    f = tm.DeviceFields.of(wd)
+    psi = wd.psi_n.clone() if psi0 is None else torch.as_tensor(psi0, device="cuda").contiguous()
+    ye = yd.ye_n.clone() if ye0 is None else torch.as_tensor(ye0, device="cuda").contiguous()
+    st, stats = ctx.ye_newton_step(f, yd, wd.psi_n, psi, ye, max_iter, rtol, raise_on_status=raise_on_status)
+    torch.cuda.synchronize()
+    return st, psi.cpu().numpy(), ye.cpu().numpy(), {k: v.cpu().numpy() for k, v in stats.items()}
+
+
+def _oracle(w, y, max_iter, rtol, psi0=None, ye0=None):
+    wn, yn = w.numpy(), y.numpy()
+    out = []
+    for r, cs in enumerate(yc.coupled_systems(wn, yn)):
+        u_n = yc.pack(wn["psi_n"][0, r], wn["psi_n"][1, r], cs.ye_n)
+        u0 = None
+        if psi0 is not None:
+            u0 = yc.pack(psi0[0, r], psi0[1, r], ye0[r])
+        out.append((cs, u_n, yc.newton(cs, u_n, u0=u0, max_iter=max_iter, rtol=rtol)))
+    return out
+
+
+def _compare(w, psi, ye, ora):
+    N = w.N
+    pe = np.stack([res.psi[:, :N] for _, _, res in ora])
+    pa = np.stack([res.psi[:, N:2 * N] for _, _, res in ora])
+    yo = np.stack([res.psi[:, 2 * N] for _, _, res in ora])
+    e = max(zone_err(psi[0], pe), zone_err(psi[1], pa))
+    ey = float(np.max(np.abs(ye - yo)) / np.max(np.abs(yo)))
+    return e, ey
+
+
+SHAPES = [
+    dict(S=2, R=3, I=1, N=1),       # single zone, single group
+    dict(S=2, R=3, I=37, N=13),     # padded groups (16): blocks of 33 rows
+    dict(S=2, R=16, I=64, N=12),
+    dict(S=2, R=4, I=24, N=20),     # blocks of 41 rows
+    dict(S=2, R=2, I=9, N=28),      # largest coupled block (57 rows)
+    dict(S=4, R=2, I=16, N=8),      # species 2, 3 present and left alone
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_coupled_newton_fixed_updates_match_oracle(shape):
+    """Exactly three coupled updates (rtol = 0) from a perturbed guess, against the oracle."""
+    say("case ye newton fixed", shape)
+    w, y = _case(**shape)
+    rng = np.random.default_rng(21)
+    psi0 = (w.psi_n.numpy() * rng.uniform(0.9, 1.1, w.psi_n.shape)).clip(0, 1)
+    ye0 = y.ye_n.numpy() + 0.003 * rng.standard_normal(y.ye_n.shape)
+    st, psi, ye, stats = _gpu(w, y, 3, 0.0, psi0, ye0)
+    assert st == tm.TM_OK
+    ora = _oracle(w, y, 3, 0.0, psi0, ye0)
+    e, ey = _compare(w, psi, ye, ora)
+    say("  psi err", e, "ye err", ey)
+    assert e < BAR and ey < BAR
+    assert np.all(stats["iters"] == 3)
+    if w.S > 2:
+        np.testing.assert_array_equal(psi[2:], psi0[2:])      # the uncoupled species are not touched
+
+
+@pytest.mark.parametrize("shape", [dict(S=2, R=16, I=64, N=12), dict(S=2, R=4, I=24, N=20)])
+def test_coupled_newton_to_tolerance_matches_oracle(shape):
+    say("case ye newton rtol", shape)
+    w, y = _case(**shape)
+    st, psi, ye, stats = _gpu(w, y, 30, 1e-12)
+    assert st == tm.TM_OK
+    ora = _oracle(w, y, 30, 1e-12)
+    e, ey = _compare(w, psi, ye, ora)
+    iters = np.array([res.iters for _, _, res in ora])
+    say("  psi err", e, "ye err", ey, "iters gpu", stats["iters"], "oracle", iters)
+    assert e < BAR and ey < BAR
+    assert np.all(np.abs(stats["iters"] - iters) <= 1)
+    assert np.all(stats["flags"] == 0)
+
+
+def test_initial_residual_norm_and_lepton_number_match_oracle():
+    """max_iter = 0: only the residual pass runs; its max|G| and lepton number against the oracle."""
+    say("case ye residual")
+    w, y = _case(S=2, R=5, I=30, N=10)
+    rng = np.random.default_rng(22)
+    psi0 = (w.psi_n.numpy() * rng.uniform(0.8, 1.2, w.psi_n.shape)).clip(0, 1)
+    ye0 = y.ye_n.numpy() + 0.01 * rng.standard_normal(y.ye_n.shape)
+    st, psi, ye, stats = _gpu(w, y, 0, 0.0, psi0, ye0)
+    assert st == tm.TM_OK
+    np.testing.assert_array_equal(psi, psi0)
+    np.testing.assert_array_equal(ye, ye0)
+    wn, yn = w.numpy(), y.numpy()
+    for r, cs in enumerate(yc.coupled_systems(wn, yn)):
+        u_n = yc.pack(wn["psi_n"][0, r], wn["psi_n"][1, r], cs.ye_n)
+        u = yc.pack(psi0[0, r], psi0[1, r], ye0[r])
+        G = yc.residual(cs, u_n, u)
+        assert abs(stats["res0_inf"][r] - np.max(np.abs(G))) <= 1e-12 * np.max(np.abs(G))
+        L = yc.lepton_number(cs, u)
+        assert abs(stats["lepton"][r] - L) <= 1e-13 * abs(L)
+
+
+def test_full_size_rays_match_oracle():
+    """Two rays at 540 zones x 20 groups (the 180-ray, four-species workload's shape), to tolerance."""
+    say("case ye full-size rays")
+    rays = [7, 131]
+    w = synth.make(1, rays=rays)
+    y = synth.ye_inputs(w, 1, rays=rays)
+    st, psi, ye, stats = _gpu(w, y, 30, 1e-12)
+    assert st == tm.TM_OK
+    ora = _oracle(w, y, 30, 1e-12)
+    e, ey = _compare(w, psi, ye, ora)
+    say("  psi err", e, "ye err", ey, "iters", stats["iters"], [res.iters for _, _, res in ora])
+    assert e < BAR and ey < BAR
+
+
+def test_lepton_number_is_conserved_on_the_gpu():
+    """Zero-flux outer boundary: the converged coupled step keeps electrons + (nu_e - anti-nu_e)."""
+    say("case ye lepton conservation")
+    w, y = _case(S=2, R=4, I=40, N=12)
+    w = dataclasses.replace(w, outer_bc=0)
+    _, _, _, s0 = _gpu(w, y, 0, 0.0)
+    st, _, ye, s1 = _gpu(w, y, 30, 1e-13)
+    assert st == tm.TM_OK
+    _, V, _, _ = oracle.geometry(w.r_edge.numpy()[0])
+    electrons = np.array([np.sum(V * y.rho.numpy()[r] * y.ye_n.numpy()[r] / yc.M_B_G) for r in range(w.R)])
+    drift = np.abs(s1["lepton"] - s0["lepton"]) / electrons
+    moved = np.abs(ye - y.ye_n.numpy()).max()
+    say("  lepton drift", drift.max(), "max |dY_e|", moved)
+    assert moved > 1e-6
+    assert np.all(drift < 1e-12)
+
+
+def test_temperature_update_matches_oracle():
+    say("case ye temperature")
+    w, y = _case(S=4, R=3, I=20, N=10)
+    rng = np.random.default_rng(23)
+    psi = (w.psi_n.numpy() * rng.uniform(0.9, 1.1, w.psi_n.shape)).clip(0, 1)
+    ye = y.ye_n.numpy() + 0.005 * rng.standard_normal(y.ye_n.shape)
+    weights = (1.0, 1.0, 2.0, 2.0)
+    wd, yd = w.to("cuda"), y.to("cuda")
+    ctx = tm.Context(tm.problem_of(wd))
+    f = tm.DeviceFields.of(wd)
+    T1 = torch.empty_like(yd.ye_n)
+    de = torch.empty_like(yd.ye_n)
+    ctx.temperature_update(f, yd, torch.as_tensor(psi, device="cuda"), torch.as_tensor(ye, device="cuda"), weights,
+                           yd.de_dT, yd.de_dye, T1, de)
+    torch.cuda.synchronize()
+    T1, de = T1.cpu().numpy(), de.cpu().numpy()
+    wn, yn = w.numpy(), y.numpy()
+    sy = oracle.systems_from_workload(wn)
+    for r, cs in enumerate(yc.coupled_systems(wn, yn)):
+        u = yc.pack(psi[0, r], psi[1, r], ye[r])
+        de_o, T_o = yc.temperature_update(cs, [sy[2][r], sy[3][r]], u, [psi[2, r], psi[3, r]], weights,
+                                          wn["temp"][r], yn["de_dT"][r], yn["de_dye"][r])
+        scale = np.max(np.abs(de_o))
+        say("  ray", r, "de err", np.max(np.abs(de[r] - de_o)) / scale, "T err", np.max(np.abs(T1[r] - T_o) / T_o))
+        assert np.max(np.abs(de[r] - de_o)) <= 1e-12 * scale
+        assert np.max(np.abs(T1[r] - T_o) / np.abs(T_o)) <= 1e-13
+
+
+def test_caller_workspace_batches_equal_one_launch():
+    say("case ye workspace batches")
+    w, y = _case(S=2, R=5, I=20, N=12)
+    _, p_all, y_all, _ = _gpu(w, y, 3, 0.0)
+    wd, yd = w.to("cuda"), y.to("cuda")
+    ctx = tm.Context(tm.problem_of(wd))
+    ctx.set_workspace(ctx.ye_workspace_bytes(2))           # batches of 2, 2, 1 rays
+    psi, ye = wd.psi_n.clone(), yd.ye_n.clone()
+    st, _ = ctx.ye_newton_step(tm.DeviceFields.of(wd), yd, wd.psi_n, psi, ye, 3, 0.0)
+    torch.cuda.synchronize()
+    assert st == tm.TM_OK
+    np.testing.assert_array_equal(psi.cpu().numpy(), p_all)
+    np.testing.assert_array_equal(ye.cpu().numpy(), y_all)
+
+
+def test_invalid_coupled_problems_are_rejected():
+    say("case ye invalid")
+    w, y = _case(S=2, R=2, I=6, N=8)
+    wd, yd = w.to("cuda"), y.to("cuda")
+    f = tm.DeviceFields.of(wd)
+    psi, ye = wd.psi_n.clone(), yd.ye_n.clone()
+    mixed = tm.Context(tm.problem_of(wd, tm.PREC_MIXED))
+    st, _ = mixed.ye_newton_step(f, yd, wd.psi_n, psi, ye, 2, 0.0, raise_on_status=False)
+    assert st == 1
+    w1 = synth.make_custom(S=1, R=2, I=6, N=8)
+    w1d = w1.to("cuda")
+    one = tm.Context(tm.problem_of(w1d))
+    st, _ = one.ye_newton_step(tm.DeviceFields.of(w1d), yd, w1d.psi_n, w1d.psi_n.clone(), ye, 2, 0.0,
+                               raise_on_status=False)
+    assert st == 1                                # a single species has no coupled pair
+    w29, y29 = _case(S=2, R=1, I=3, N=29)
+    w29d, y29d = w29.to("cuda"), y29.to("cuda")
+    big = tm.Context(tm.problem_of(w29d))
+    st, _ = big.ye_newton_step(tm.DeviceFields.of(w29d), y29d, w29d.psi_n, w29d.psi_n.clone(), y29d.ye_n.clone(), 2,
+                               0.0, raise_on_status=False)
+    assert st == 1
+
+
+def test_one_context_alternates_coupled_and_single_species_steps():
+    """A context that sized its own workspace for one step kind serves the other one too."""
+    say("case ye alternate with single-species step")
+    w, y = _case(S=2, R=3, I=16, N=8)
+    wd, yd = w.to("cuda"), y.to("cuda")
+    f = tm.DeviceFields.of(wd)
+    fresh = tm.Context(tm.problem_of(wd))
+    p_ref = wd.psi_n.clone()
+    fresh.newton_step(f, wd.psi_n, p_ref, 3, 0.0)
+    ctx = tm.Context(tm.problem_of(wd))
+    psi, ye = wd.psi_n.clone(), yd.ye_n.clone()
+    ctx.ye_newton_step(f, yd, wd.psi_n, psi, ye, 3, 0.0)
+    p1 = wd.psi_n.clone()
+    ctx.newton_step(f, wd.psi_n, p1, 3, 0.0)
+    psi2, ye2 = wd.psi_n.clone(), yd.ye_n.clone()
+    ctx.ye_newton_step(f, yd, wd.psi_n, psi2, ye2, 3, 0.0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(p1.cpu().numpy(), p_ref.cpu().numpy())
+    np.testing.assert_array_equal(psi2.cpu().numpy(), psi.cpu().numpy())
+    np.testing.assert_array_equal(ye2.cpu().numpy(), ye.cpu().numpy())

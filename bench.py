@@ -8,7 +8,8 @@ factorisation, FP64 residual/update/sums) refined to a 1e-12 relative residual.
 Alongside, the FP64 path is timed to the same tolerance (time-to-tolerance and the
 mixed-vs-FP64 error are reported), the FP64 adjoint of the outer luminosity, and the
 configuration's multi-step job (10 drifting steps, then the adjoint over all of them with
-one checkpoint per step).
+one checkpoint per step), and the FP64 Y_e-coupled step of species 0 and 1 (blocks of 2N+1
+rows coupling the electron neutrinos, antineutrinos and the electron fraction of each zone).
 
 Metric: Newton updates/s = sum over systems of (Newton updates applied) x I x N / time.
 Output: one JSON line on stdout (progress goes to stderr).
@@ -187,6 +188,57 @@ def multistep_leg(tm, torch, synth, dev, rays, steps, rtol, max_iter):
                 adjoint_precision="fp64", adjoint_factor_batch=batch, checkpoints=steps, gradient_finite=finite)
 
 
+def ye_factor_flops_per_zone(N: int) -> float:
+    """Algorithmic flops of one coupled block of M = 2N+1 rows (nu_e, anti-nu_e, Y_e) per zone and
+    Newton update: in-place Gauss-Jordan on [A | diag(b) | g], M steps of (M-1) row updates of M+1
+    entries (2M(M^2-1)), plus the Schur update diag(bm) C and the back substitution (4M^2)."""
+    M = 2 * N + 1
+    return 2.0 * M * (M * M - 1) + 4.0 * M * M
+
+
+def ye_factor_bytes_per_zone(N: int) -> float:
+    """Algorithmic HBM bytes of one coupled block per zone and launch: 2N cells reading psi, kappa_a,
+    eta, kappa_s, the residual and the two Y_e derivatives and writing the update (8 x 8 B), plus the
+    stored factors C_i and y_i ((2N+1) x (2N+1) doubles) written forward and read back."""
+    M = 2 * N + 1
+    return 2 * N * 64.0 + 2.0 * M * M * 8
+
+
+def ye_leg(tm, torch, synth, w, f, rays, steps, warmup, rtol, max_iter):
+    """FP64 Y_e-coupled Newton step of species 0 and 1 of every ray (block 2N+1) to the same rule."""
+    y = synth.ye_inputs(w, 4, rays=rays)
+    ctx = tm.Context(tm.problem_of(w, tm.PREC_FP64))
+    ctx.set_workspace(ctx.ye_workspace_bytes(0))
+    psi = torch.empty_like(w.psi_n)
+    ye = torch.empty_like(y.ye_n)
+    times, iters, st, stats = [], None, None, None
+    for s in range(warmup + steps):
+        psi.copy_(w.psi_n)
+        ye.copy_(y.ye_n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stats = ctx.ye_newton_step(f, y, w.psi_n, psi, ye, max_iter, rtol, raise_on_status=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        iters = stats["iters"].to(torch.int64)
+        log(f"  {'warm' if s < warmup else 'step'} {s}: {1e3 * (t1 - t0):.1f} ms, iters min {int(iters.min())} "
+            f"max {int(iters.max())}, status {tm.STATUS_NAMES.get(st, st)}")
+        if s >= warmup:
+            times.append(t1 - t0)
+    upd = int(iters.sum().item())                      # coupled block updates (ray x update)
+    t = sum(times) / len(times)
+    zones_upd = upd * w.I
+    res = dict(status=tm.STATUS_NAMES.get(st, st), flags_max=int(stats["flags"].max().item()))
+    ctx.close()
+    del psi, ye, y
+    torch.cuda.empty_cache()
+    return dict(ms_per_step=1e3 * t, value=zones_upd * 2 * w.N / t, unit="updates/s (nu_e and anti-nu_e cells)",
+                mean_iters=float(iters.double().mean()), precision="fp64", block=2 * w.N + 1,
+                factor_flops_per_update=ye_factor_flops_per_zone(w.N) * w.R * w.I,
+                factor_bytes_per_update=ye_factor_bytes_per_zone(w.N) * w.R * w.I,
+                **res)
+
+
 def cpu_baseline(sample_systems: int, workers: int):
     """The FP64 oracle (as written, untuned) on a bounded sample of systems of the same workload."""
     import multiprocessing as mp
@@ -247,6 +299,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multistep", type=int, default=10,
                     help="steps of the multi-step leg (drifting inputs, checkpointed adjoint); 0 skips it")
+    ap.add_argument("--ye-steps", type=int, default=1,
+                    help="timed steps of the FP64 Y_e-coupled leg (species 0 and 1 with Y_e); 0 skips it")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short pass for rocprofv3: one mixed step, one launch of each timed kernel, "
@@ -325,13 +379,19 @@ def main(argv=None):
         del psi_d
         torch.cuda.empty_cache()
 
+    out_ye = None
+    if a.ye_steps > 0:
+        log("FP64 Y_e-coupled Newton (species 0 and 1 with Y_e)")
+        out_ye = ye_leg(tm, torch, synth, w, f, rays, a.ye_steps, 0 if a.profile_pass else 1, a.rtol, a.max_iter)
+
     value = sum(u_m) / sum(t_m)
     ms = 1e3 * sum(t_m) / len(t_m)
     flops_launch = factor_flops_per_cell(w.N) * cells
     bytes_launch = factor_bytes_per_cell(w.N, 4) * cells
     t_hbm, t_alu = bytes_launch / (PEAK_HBM_GBS * 1e9), flops_launch / (PEAK_VALU_TFLOPS * 1e12)
     kernel_src = os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_factor.hip")
-    tr = traffic_record(kernel_src)
+    # the counters were taken on the full 16384-ray launch; a reduced run reports none
+    tr = traffic_record(kernel_src) if rays is None else None
     # the roofline time of the launch is max(HBM time, VALU time); with stored factors it is HBM
     achieved = bytes_launch / t_fac / 1e9
     roof = dict(bound="hbm" if t_hbm >= t_alu else "alu", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
@@ -370,6 +430,7 @@ def main(argv=None):
         "fp64": out_fp64,
         "mixed_vs_fp64_speedup": (out_fp64["ms_per_step"] / ms) if out_fp64 else None,
         "adjoint_fp64": out_adj,
+        "ye_coupled_fp64": out_ye,
         "multistep": multi,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -11,7 +11,9 @@ Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
 must never be used as a fallback for it.
 
 The Y_e-coupled step (electron-fraction equation, eq. a62a, and the temperature update, eqs.
-a62b and a62d) is in `oracle.ye_coupled`.
+a62b and a62d) is in `oracle.ye_coupled`; the energy-advection step (Lagrangian energy shift,
+PPM remap, Pauli over-fill limiter, lapse remap; eqs. a78-a81d, p1-p8) in
+`oracle.energy_advection`, pinned by `tests/test_oracle_energy.py`.
 
 Parity status: every function below is pinned by `tests/test_oracle_pins.py`
 (closed forms, invariants, brute-force dense solves, finite differences);
@@ -25,3 +27,4 @@ from .transport import (  # noqa: F401
     newton_batch, residual_batch, multistep_forward, multistep_objective, multistep_adjoint,
 )
 from . import ye_coupled  # noqa: F401
+from . import energy_advection  # noqa: F401

@@ -8,8 +8,9 @@ factorisation, FP64 residual/update/sums) refined to a 1e-12 relative residual.
 Alongside, the FP64 path is timed to the same tolerance (time-to-tolerance and the
 mixed-vs-FP64 error are reported), the FP64 adjoint of the outer luminosity, and the
 configuration's multi-step job (10 drifting steps, then the adjoint over all of them with
-one checkpoint per step), and the FP64 Y_e-coupled step of species 0 and 1 (blocks of 2N+1
-rows coupling the electron neutrinos, antineutrinos and the electron fraction of each zone).
+one checkpoint per step), the FP64 Y_e-coupled step of species 0 and 1 (blocks of 2N+1
+rows coupling the electron neutrinos, antineutrinos and the electron fraction of each zone), and
+the energy-advection update of every zone (Lagrangian energy shift, PPM remap, over-fill limiter).
 
 Metric: Newton updates/s = sum over systems of (Newton updates applied) x I x N / time.
 Output: one JSON line on stdout (progress goes to stderr).
@@ -239,6 +240,31 @@ def ye_leg(tm, torch, synth, w, f, rays, steps, warmup, rtol, max_iter):
                 **res)
 
 
+def energy_bytes(cells: int, zones: int) -> float:
+    """Algorithmic HBM bytes of one energy-advection launch: read psi and the Eddington factor and write
+    psi (3 x 8 B per cell), and six zone arrays (rho, lapse before and after, dR/R, db/b) once per zone."""
+    return 24.0 * cells + 48.0 * zones
+
+
+def energy_leg(tm, torch, synth, w, rays, reps):
+    """Energy-advection update (Lagrangian energy shift, PPM remap, over-fill limiter) of every zone of
+    the workload: one launch timed with HIP events on the library's stream, `reps` times."""
+    e = synth.eadv_inputs(w, 4, rays=rays)
+    ctx = tm.Context(tm.problem_of(w, tm.PREC_FP64))
+    psi = w.psi_n.clone()
+    kw = dict(rho_old=e.rho_old, rho_new=e.rho_new, lapse_old=e.lapse_old, lapse_new=e.lapse_new, dlnR=e.dlnR,
+              dlnb=e.dlnb, eddington=e.eddington)
+    t = time_kernel(torch, lambda: ctx.energy_advect(w.e_edge, psi, **kw), reps)
+    ctx.close()
+    del psi, e
+    torch.cuda.empty_cache()
+    cells, zones = w.n_cells, w.R * w.I
+    b = energy_bytes(cells, zones)
+    return dict(kernel="k_energy_advect<20>", kernel_ms=1e3 * t, cells_per_s=cells / t,
+                zone_updates_per_s=w.S * zones / t, algorithmic_bytes_per_launch=b, achieved_gbs=b / t / 1e9,
+                hbm_frac=b / t / 1e9 / PEAK_HBM_GBS)
+
+
 def cpu_baseline(sample_systems: int, workers: int):
     """The FP64 oracle (as written, untuned) on a bounded sample of systems of the same workload."""
     import multiprocessing as mp
@@ -379,6 +405,9 @@ def main(argv=None):
         del psi_d
         torch.cuda.empty_cache()
 
+    log("energy advection (Lagrangian shift, PPM remap, over-fill limiter)")
+    out_energy = energy_leg(tm, torch, synth, w, rays, a.kernel_reps)
+
     out_ye = None
     if a.ye_steps > 0:
         log("FP64 Y_e-coupled Newton (species 0 and 1 with Y_e)")
@@ -431,6 +460,7 @@ def main(argv=None):
         "mixed_vs_fp64_speedup": (out_fp64["ms_per_step"] / ms) if out_fp64 else None,
         "adjoint_fp64": out_adj,
         "ye_coupled_fp64": out_ye,
+        "energy_advection": out_energy,
         "multistep": multi,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -285,6 +285,60 @@ tm_status tm_temperature_update(tm_ctx *ctx, const tm_inputs *in, const tm_ye_in
                                 const double *de_dT, const double *de_dye, double *de_out,
                                 double *temp_out);
 
+/* ---------------------------------------------------------------------------------
+ * Energy advection (eqs. a78-a81d) and the remap after a change of the lapse (eqs. p1-p8).
+ *
+ * Per (species, ray, zone), over the N groups of the shared energy grid e_edge (in->e_edge):
+ *  1. Lagrangian energy step (TM_EADV_LAGRANGIAN, eqs. a78-a80): every group edge E_m moves to
+ *       E'_m = [1 + (a^{n+1}/a^n - 1 - dR/R) - (db/b - dR/R) eta2_m] E_m            (eq. a79)
+ *     with eta2_m the scalar Eddington factor at the edge (mean of the two adjacent groups, the end
+ *     edges the end group's value, 1/3 when `eddington` is NULL), and the number per unit mass is
+ *     kept: psi'_k W'_k = (rho a^3)^{n+1} / (rho a^3)^n psi_k W_k                    (eq. a78).
+ *     Lapse change (TM_EADV_LAPSE, eqs. p1, p2): the local grid E/a moves from E/a^n to E/a^{n+1}
+ *     and psi_k W_k(E/a^n) neutrinos sit in group k.
+ *  2. Remap onto the fixed grid (eq. a81; eqs. p5-p8): the number per unit energy (proportional to
+ *     eps^2 psi) is given a piecewise parabolic profile on the displaced grid (eqs. h9-h24 in
+ *     their planar form; two ghost groups at each end repeat the end group; each group's edge
+ *     values adjusted so that its parabola has no interior extremum), and through each
+ *     interior edge passes the number between the displaced and the fixed edge (eqs. h60, h61);
+ *     no number passes the two outer edges.  The fluxes are scaled by
+ *       xi = (E_before - sum_k N_k eps_k) / sum_k (F_{k-1/2} - F_{k+1/2}) eps_k       (eq. p8)
+ *     (1 when the denominator is 0), which keeps the energy as well as the number (eq. p6).
+ *  3. Over-fill limiter (eqs. a81a-a81d): from the lowest group while groups k+1 and k+2 exist, an
+ *     excess psi_k - 1 > 0 is removed and added to group k+1 and removed from group k+2 so that
+ *     number and energy are kept; a removal larger than psi_{k+2} is scaled down so that
+ *     psi_{k+2} becomes 0 (the paper's approximate case, flagged).
+ * psi (cell, in place) holds psi^n on entry and the new psi on return.  A zone whose swept region at
+ * some edge is wider than the group it comes from, or whose displaced grid is not increasing, is
+ * left unchanged and flagged.  Asynchronous; no workspace.
+ * --------------------------------------------------------------------------------- */
+
+#define TM_EADV_LAGRANGIAN 0
+#define TM_EADV_LAPSE      1
+
+#define TM_EADV_FLAG_DISPLACEMENT  1   /* displacement beyond a group: zone left unchanged      */
+#define TM_EADV_FLAG_OVERFILL      2   /* the over-fill limiter moved neutrinos                 */
+#define TM_EADV_FLAG_OVERFILL_CLAMP 4  /* ... and hit the psi_{k+2} >= 0 bound (approximate)     */
+
+typedef struct {
+    int32_t mode;               /* TM_EADV_LAGRANGIAN or TM_EADV_LAPSE                          */
+    const double *rho_old;      /* zone [R][I] g cm^-3 before and after the hydro step; both or   */
+    const double *rho_new;      /*   neither (NULL: no change); Lagrangian mode only              */
+    const double *lapse_old;    /* zone [R][I] lapse a^n and a^{n+1} (> 0); both or neither (NULL: */
+    const double *lapse_new;    /*   a = 1); required in the lapse mode                           */
+    const double *dlnR;         /* zone [R][I]: dR/R and db/b of the hydro step (NULL: 0);         */
+    const double *dlnb;         /*   Lagrangian mode only                                         */
+    const double *eddington;    /* cell: scalar Eddington factor psi^(2)/psi^(0) (NULL: 1/3);     */
+                                /*   Lagrangian mode only                                         */
+} tm_eadv_inputs;
+
+/* Apply the energy-advection update to psi (cell, in place).  Needs in->e_edge only.  xi (sysz
+ * [S][R][I], may be NULL) receives the flux scale of eq. p8 (1 where nothing moved or the zone was
+ * left unchanged); flags (sysz, may be NULL) the TM_EADV_FLAG_* bits of each zone.  Returns
+ * TM_ERR_INVALID_ARG for a missing pointer, an unknown mode or half of an input pair.           */
+tm_status tm_energy_advect(tm_ctx *ctx, const tm_inputs *in, const tm_eadv_inputs *ea, double *psi,
+                           double *xi, int32_t *flags);
+
 /* Human-readable name of a status code (static storage).                          */
 const char *tm_status_string(tm_status status);
 

@@ -7,7 +7,7 @@ Advection due to Changes in the Lapse" in the transport appendix, with the PPM m
 * eqs. a78-a80: the Lagrangian energy step.  The group edges are displaced by the factor of
   eq. a79 and psi is rescaled so that the number of neutrinos per unit mass is unchanged;
 * eq. a81 with eqs. p5-p8: the remap of the displaced grid back onto the fixed grid.  The number
-  density per unit energy, eps^2 psi, gets a piecewise parabolic profile in energy; the number in
+  density per unit energy, eps^2 psi, gets a piecewise parabolic profile in energy (eqs. h9-h24); the number in
   the region swept by each edge moves across it, and the fluxes are scaled by one factor xi per
   zone so that the energy is conserved as well as the number;
 * eqs. a81a-a81d: the Pauli over-fill limiter, which moves the excess of an over-filled group to
@@ -33,11 +33,18 @@ Readings (the paper is silent, garbled or inconsistent here; each is listed in D
     fraction y of a zone gives (1 - 2y/3), the same factor as eq. h60 (the pins integrate the
     parabola numerically);
   * eq. h11 with Delta a_{i+1/2} Delta a_{i-1/2} = 0 gives a zero slope (a flat side);
+  * the paper states that its monotonicity constraints keep new maxima and minima from appearing, but
+    prints only the limits on the slopes and edge values (eqs. h11, h15, h16), which do not keep the
+    parabola of a zone from overshooting inside it; on a steeply falling spectrum the overshoot goes
+    below zero and the remap then produces negative occupations.  The zone constraint of the PPM
+    paper it cites (Colella and Woodward 1984) is applied to each group's edge values before the
+    parabola is formed: flat at a local extremum of the averages, otherwise the far edge moved until
+    the parabola's extremum sits on the zone edge;
   * two ghost groups at each end of the energy grid repeat the end group's average and width, and
     the fluxes through the two outer grid edges are zero (the paper's condition for eq. p5 to
     conserve number);
-  * edge displacement: a swept region wider than the group it comes from is outside the method;
-    such a zone is left unchanged and flagged;
+  * edge displacement: a swept region wider than the group it comes from, or a displaced grid that
+    is no longer increasing, is outside the method; such a zone is left unchanged and flagged;
   * the Eddington factor of eq. a79 at a group edge is the mean of the two adjacent groups' values
     (the end edges take the adjacent group's value); without one, 1/3 (the diffusion limit);
   * eq. p8 prints the denominator without its sum over k; it is sum_k (F_{k-1/2} - F_{k+1/2}) eps_k
@@ -130,6 +137,19 @@ def parabola(a: np.ndarray, aL: np.ndarray, aR: np.ndarray):
     return aR - aL, 6.0 * (a - 0.5 * (aL + aR))
 
 
+def monotone_edges(a: np.ndarray, aL: np.ndarray, aR: np.ndarray):
+    """Edge values of each zone adjusted so that its parabola has no extremum inside the zone: flat at a
+    local extremum of the averages, else the edge on the far side of an interior extremum is moved
+    until the extremum sits on the zone edge (the zone constraint of Colella and Woodward's PPM)."""
+    Da, a6 = parabola(a, aL, aR)
+    flat = (aR - a) * (a - aL) <= 0.0
+    lo_fix = ~flat & (Da * a6 > Da * Da)
+    hi_fix = ~flat & (-Da * Da > Da * a6)
+    aL2 = np.where(flat, a, np.where(lo_fix, 3.0 * a - 2.0 * aR, aL))
+    aR2 = np.where(flat, a, np.where(hi_fix, 3.0 * a - 2.0 * aL, aR))
+    return aL2, aR2
+
+
 def average_top(aR, Da, a6, y):
     """Mean of the parabola of eq. h22 over the top fraction y of its zone (eq. h60, the swept width in
     place of c_s dt)."""
@@ -151,7 +171,7 @@ def remap_fluxes(N: np.ndarray, src_edges: np.ndarray, tgt_edges: np.ndarray):
     swept region at some edge is wider than the group it is taken from."""
     dS = src_edges[..., 1:] - src_edges[..., :-1]
     a = N / dS
-    aL, aR = ppm_interfaces(a, dS)
+    aL, aR = monotone_edges(a, *ppm_interfaces(a, dS))
     Da, a6 = parabola(a, aL, aR)
     delta = src_edges[..., 1:-1] - tgt_edges[..., 1:-1]          # eq. h101 at interior edges
     up = delta > 0.0
@@ -160,7 +180,7 @@ def remap_fluxes(N: np.ndarray, src_edges: np.ndarray, tgt_edges: np.ndarray):
     f_up = average_top(aR[..., :-1], Da[..., :-1], a6[..., :-1], y_up) * delta
     f_dn = average_bottom(aL[..., 1:], Da[..., 1:], a6[..., 1:], y_dn) * delta
     inner = np.where(delta == 0.0, 0.0, np.where(up, f_up, f_dn))
-    ok = np.all((y_up <= 1.0) & (y_dn <= 1.0), axis=-1)
+    ok = np.all((y_up <= 1.0) & (y_dn <= 1.0), axis=-1) & np.all(dS > 0.0, axis=-1)
     zero = np.zeros(N.shape[:-1] + (1,))
     return np.concatenate([zero, inner, zero], axis=-1), ok
 

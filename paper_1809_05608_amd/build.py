@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_ye.hip"]
+SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_ye.hip", "tm_energy.hip"]
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -731,6 +731,40 @@ tm_status tm_temperature_update(tm_ctx* c, const tm_inputs* in, const tm_ye_inpu
                      "temperature kernel");
 }
 
+tm_status tm_energy_advect(tm_ctx* c, const tm_inputs* in, const tm_eadv_inputs* ea, double* psi, double* xi,
+                           int32_t* flags) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if (!in || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "e_edge is required");
+    if (!ea) return set_err(c, TM_ERR_INVALID_ARG, "energy-advection inputs are NULL");
+    if (!psi) return set_err(c, TM_ERR_INVALID_ARG, "psi is required");
+    if (ea->mode != TM_EADV_LAGRANGIAN && ea->mode != TM_EADV_LAPSE)
+        return set_err(c, TM_ERR_INVALID_ARG, "mode must be TM_EADV_LAGRANGIAN or TM_EADV_LAPSE");
+    if (!ea->rho_old != !ea->rho_new) return set_err(c, TM_ERR_INVALID_ARG, "rho_old and rho_new go together");
+    if (!ea->lapse_old != !ea->lapse_new)
+        return set_err(c, TM_ERR_INVALID_ARG, "lapse_old and lapse_new go together");
+    if (ea->mode == TM_EADV_LAPSE && !ea->lapse_old)
+        return set_err(c, TM_ERR_INVALID_ARG, "the lapse mode needs lapse_old and lapse_new");
+    tmk::EaArgs a;
+    a.mode = ea->mode == TM_EADV_LAPSE ? tmk::kEaLapse : tmk::kEaLagrangian;
+    a.N = c->p.n_groups;
+    a.RI = (long long)c->p.n_rays * c->p.n_zones;
+    a.nz = (long long)c->p.n_species * a.RI;
+    a.e_edge = in->e_edge;
+    const bool lag = a.mode == tmk::kEaLagrangian;
+    a.rho_old = lag ? ea->rho_old : nullptr;
+    a.rho_new = lag ? ea->rho_new : nullptr;
+    a.a_old = ea->lapse_old;
+    a.a_new = ea->lapse_new;
+    a.dlnR = lag ? ea->dlnR : nullptr;
+    a.dlnb = lag ? ea->dlnb : nullptr;
+    a.edd = lag ? ea->eddington : nullptr;
+    a.psi = psi;
+    a.xi = xi;
+    a.flags = flags;
+    TM_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    return hip_check(c, tmk::launch_energy_advect(a, c->stream), "energy-advection kernel");
+}
+
 tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, double* seed) {
     if (!c) return TM_ERR_INVALID_ARG;
     if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");

@@ -164,6 +164,28 @@ hipError_t launch_ye_temperature(const Shape& sh, const Fields& f, const YeField
 size_t ye_ws_bytes_per_ray(int I, int N);
 constexpr int kYeMaxGroups = 28;          // 2 NT + 1 rows of a coupled block fit one wavefront
 
+// Energy advection (eqs. a78-a81d) and lapse remap (eqs. p1-p8), one thread per (species, ray, zone).
+constexpr int kEaLagrangian = 0, kEaLapse = 1;                            // TM_EADV_* modes
+constexpr int kEaDisplacement = 1, kEaOverfill = 2, kEaOverfillClamp = 4;  // TM_EADV_FLAG_* bits
+struct EaArgs {
+    int mode;
+    int N;
+    long long nz;             // zone-systems S * R * I
+    long long RI;             // zones per species, R * I
+    const double* e_edge;     // [N+1] target grid
+    const double* rho_old;    // zone [R][I], nullable
+    const double* rho_new;
+    const double* a_old;      // lapse, zone, nullable (required in the lapse mode)
+    const double* a_new;
+    const double* dlnR;       // zone, nullable
+    const double* dlnb;
+    const double* edd;        // cell, nullable (1/3)
+    double* psi;              // cell, in place
+    double* xi;               // sysz, nullable
+    int* flags;               // sysz, nullable
+};
+hipError_t launch_energy_advect(const EaArgs& a, hipStream_t st);
+
 // Factor workspace: C and y per system slot; a batch of b systems takes b + kWsPadSystems slots (the
 // layout is interleaved by wave group of at most 16 systems, and a last partial group keeps empty slots).
 constexpr int kWsPadSystems = 15;

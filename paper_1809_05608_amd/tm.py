@@ -24,10 +24,12 @@ STATUS_NAMES = {0: "TM_OK", 1: "TM_ERR_INVALID_ARG", 2: "TM_ERR_HIP", 3: "TM_ERR
 TERM_DIFFUSION, TERM_EMABS, TERM_NES = 1, 2, 4
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_ZERO_PIVOT, FLAG_PIVOT_FALLBACK = 1, 2, 4, 8
+EADV_LAGRANGIAN, EADV_LAPSE = 0, 1
+EADV_FLAG_DISPLACEMENT, EADV_FLAG_OVERFILL, EADV_FLAG_OVERFILL_CLAMP = 1, 2, 4
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
             "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_workspace_bytes",
-            "tm_ye_newton_step", "tm_temperature_update", "tm_status_string", "tm_last_error"]
+            "tm_ye_newton_step", "tm_temperature_update", "tm_energy_advect", "tm_status_string", "tm_last_error"]
 
 
 class TMError(RuntimeError):
@@ -55,6 +57,12 @@ class Stats(ctypes.Structure):
 
 class YeInputs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("rho", "ye_n", "dka_dye", "deta_dye")]
+
+
+class EadvInputs(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32)] + [(n, ctypes.c_void_p) for n in
+                                             ("rho_old", "rho_new", "lapse_old", "lapse_new", "dlnR", "dlnb",
+                                              "eddington")]
 
 
 class YeStats(ctypes.Structure):
@@ -87,13 +95,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_ye_workspace_bytes.restype = ctypes.c_size_t
     lib.tm_ye_newton_step.argtypes = [V, P(Inputs), P(YeInputs), V, V, V, I32, D, P(YeStats)]
     lib.tm_temperature_update.argtypes = [V, P(Inputs), P(YeInputs), V, V, P(D), V, V, V, V]
+    lib.tm_energy_advect.argtypes = [V, P(Inputs), P(EadvInputs), V, V, V]
     lib.tm_status_string.argtypes = [ctypes.c_int]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = [V]
     lib.tm_last_error.restype = ctypes.c_char_p
     for name in ("tm_create", "tm_destroy", "tm_set_workspace", "tm_assemble", "tm_factor_solve",
                  "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_newton_step",
-                 "tm_temperature_update"):
+                 "tm_temperature_update", "tm_energy_advect"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -314,6 +323,33 @@ class Context:
         inp, yin = self._inputs(f), self._ye_inputs(y)
         self._check(self.lib.tm_temperature_update(self._h, ctypes.byref(inp), ctypes.byref(yin), _ptr(psi), _ptr(ye),
                                                    w, _ptr(de_dT), _ptr(de_dye), _ptr(de_out), _ptr(temp_out)))
+
+    def energy_advect(self, e_edge, psi, *, mode=EADV_LAGRANGIAN, rho_old=None, rho_new=None, lapse_old=None,
+                      lapse_new=None, dlnR=None, dlnb=None, eddington=None, xi=None, flags=None):
+        """Energy-advection update of psi in place (eqs. a78-a81d, or the lapse remap of eqs. p1-p8).
+
+        e_edge [N+1]; zone arrays [R][I]; eddington a cell array; xi (float64) and flags (int32) [S][R][I]."""
+        p = self.problem
+        self._cell(psi, "psi")
+        if e_edge.dtype != torch.float64 or e_edge.device != self.device or tuple(e_edge.shape) != (p.n_groups + 1,):
+            raise ValueError(f"e_edge must be a float64 tensor of shape {(p.n_groups + 1,)} on {self.device}")
+        zones = {"rho_old": rho_old, "rho_new": rho_new, "lapse_old": lapse_old, "lapse_new": lapse_new,
+                 "dlnR": dlnR, "dlnb": dlnb}
+        for name, t in zones.items():
+            if t is not None:
+                self._zone(t, name)
+        if eddington is not None:
+            self._cell(eddington, "eddington")
+        sysz = (p.n_species, p.n_rays, p.n_zones)
+        for name, t, dt in (("xi", xi, torch.float64), ("flags", flags, torch.int32)):
+            if t is not None and (t.dtype != dt or t.device != self.device or not t.is_contiguous()
+                                  or tuple(t.shape) != sysz):
+                raise ValueError(f"{name} must be a contiguous {dt} tensor of shape {sysz} on {self.device}")
+        inp = Inputs(None, _ptr(e_edge), None, None, None, None, None, None)
+        ea = EadvInputs(int(mode), *[_ptr(zones[n]) for n in ("rho_old", "rho_new", "lapse_old", "lapse_new",
+                                                              "dlnR", "dlnb")], _ptr(eddington))
+        self._check(self.lib.tm_energy_advect(self._h, ctypes.byref(inp), ctypes.byref(ea), _ptr(psi), _ptr(xi),
+                                              _ptr(flags)))
 
     def luminosity_seed(self, f: DeviceFields, seed, add=None):
         """seed = dL_N/dpsi (outer-boundary number luminosity) + add (cell arrays)."""

@@ -295,6 +295,62 @@ def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step:
     return YeInputs(rho=rho, ye_n=ye_n, dka_dye=dka, deta_dye=deta, de_dT=de_dT, de_dye=de_dye)
 
 
+@dataclasses.dataclass
+class EadvInputs:
+    """Inputs of the energy-advection step of a workload between its drift steps `step` and `step + 1`.
+
+    rho_old, rho_new [R][I] g/cm^3; lapse_old, lapse_new [R][I]; dlnR, dlnb [R][I] (fractional changes
+    of the areal radius and of the radial stretch over the hydro step); eddington [S][R][I][N].
+    """
+    rho_old: torch.Tensor
+    rho_new: torch.Tensor
+    lapse_old: torch.Tensor
+    lapse_new: torch.Tensor
+    dlnR: torch.Tensor
+    dlnb: torch.Tensor
+    eddington: torch.Tensor
+
+    def numpy(self) -> dict:
+        return {f.name: getattr(self, f.name).cpu().numpy() for f in dataclasses.fields(self)}
+
+
+LAPSE_R0_CM = 2.04e5        # the paper's redshift test: a(R) = sqrt(1 - R0/R), R0 = 2.04 km
+R_NU_CM = 3.0e6             # neutrinosphere radius of a 10 MeV neutrino in the Eddington-factor stand-in
+
+
+def eadv_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0,
+                R_full: Optional[int] = None) -> EadvInputs:
+    """Synthetic energy-advection inputs for workload `w` (made by `make(cfg, rays=rays, step=step)`).
+
+    * rho before and after: the workload's density at drift steps `step` and `step + 1`;
+    * a homologous stand-in for the hydro step, dR/R = db/b = -(1/3) ln(rho_new/rho_old);
+    * lapse a = sqrt(1 - R0/r) at the zone centre, with R0 growing by 1% per step;
+    * Eddington factor 1/3 + (2/3) x^2/(1 + x^2), x = r / (R_nu (eps/10 MeV)^0.5): 1/3 (diffusion) deep
+      inside, rising towards 1 (free streaming) outside a group-dependent neutrinosphere.
+    """
+    if R_full is None:
+        R_full = CONFIGS[cfg]["R"]
+    if rays is None:
+        rays = range(R_full)
+    rays = np.asarray(rays, dtype=np.int64)
+    rho0, _, r_edge = _profiles(cfg, R_full, w.I, rays, step)
+    rho1, _, _ = _profiles(cfg, R_full, w.I, rays, step + 1)
+    dev = w.kappa_a.device
+    f64 = torch.float64
+    rc = 0.5 * (r_edge[1:] + r_edge[:-1])
+    a0 = np.sqrt(1.0 - LAPSE_R0_CM * 1.01 ** step / rc)
+    a1 = np.sqrt(1.0 - LAPSE_R0_CM * 1.01 ** (step + 1) / rc)
+    dln = -np.log(rho1 / rho0) / 3.0
+    eps = _group_energies(w.e_edge.to(dev)).cpu().numpy()
+    x = rc[:, None] / (R_NU_CM * np.sqrt(eps / 10.0))[None, :]                 # [I][N]
+    edd = 1.0 / 3.0 + (2.0 / 3.0) * x * x / (1.0 + x * x)
+    t = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=f64, device=dev)
+    R = len(rays)
+    zone = lambda v: t(np.broadcast_to(v, (R, w.I)))
+    return EadvInputs(rho_old=t(rho0), rho_new=t(rho1), lapse_old=zone(a0), lapse_new=zone(a1), dlnR=t(dln),
+                      dlnb=t(dln), eddington=t(edd).expand(w.S, R, w.I, w.N).contiguous())
+
+
 def make(cfg: int, *, rays: Optional[Sequence[int]] = None, zones: Optional[int] = None,
          groups: Optional[int] = None, species: Optional[int] = None, step: int = 0,
          device="cpu") -> Workload:

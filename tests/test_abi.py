@@ -34,7 +34,7 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"tm_problem": tm.Problem, "tm_inputs": tm.Inputs, "tm_stats": tm.Stats,
-               "tm_ye_inputs": tm.YeInputs, "tm_ye_stats": tm.YeStats}
+               "tm_ye_inputs": tm.YeInputs, "tm_ye_stats": tm.YeStats, "tm_eadv_inputs": tm.EadvInputs}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -113,3 +113,8 @@ def test_ye_entry_points_reject_a_null_context():
     lib = tm.load_library()
     assert lib.tm_ye_newton_step(None, None, None, None, None, None, 1, 0.0, None) == 1
     assert lib.tm_temperature_update(None, None, None, None, None, None, None, None, None, None) == 1
+
+
+def test_energy_advect_rejects_a_null_context():
+    lib = tm.load_library()
+    assert lib.tm_energy_advect(None, None, None, None, None, None) == 1

@@ -96,6 +96,36 @@ def test_monotonicity_limits():
     assert np.array_equal(aL[1:], aR[:-1])
 
 
+def test_zone_constraint_keeps_parabolas_free_of_interior_extrema():
+    """After the zone constraint no group parabola has an extremum strictly inside its group, so every
+    swept-region mean lies between the group's edge values, and the parabolas of a positive, steeply
+    falling spectrum stay non-negative."""
+    e = np.geomspace(2.0, 300.0, 21)
+    eps = ea.centers(e)
+    psi = 1.0 / (np.exp((eps - 6.0) / 3.0) + 1.0)
+    a = psi * ea.weights(e) / np.diff(e)
+    aL, aR = ea.monotone_edges(a, *ea.ppm_interfaces(a, np.diff(e)))
+    Da, a6 = ea.parabola(a, aL, aR)
+    x = np.linspace(0.0, 1.0, 201)[:, None]
+    prof = aL + x * (Da + a6 * (1.0 - x))
+    assert np.all(prof >= np.minimum(aL, aR) - 1e-15 * np.abs(a)) and np.all(prof >= 0.0)
+    assert np.all(prof <= np.maximum(aL, aR) + 1e-15 * np.abs(a))
+    # without the constraint the same spectrum has parabolas dipping below zero
+    aL0, aR0 = ea.ppm_interfaces(a, np.diff(e))
+    Da0, a60 = ea.parabola(a, aL0, aR0)
+    assert np.any(aL0 + x * (Da0 + a60 * (1.0 - x)) < 0.0)
+
+
+def test_remap_of_a_steep_spectrum_stays_non_negative():
+    e = np.geomspace(2.0, 300.0, 21)
+    eps = ea.centers(e)
+    T = np.linspace(3.0, 12.0, 32)[:, None]
+    psi = 0.9 / (np.exp((eps - 2.0 * T) / T) + 1.0)
+    for s in (0.99, 1.01):
+        out, xi, flags = ea.lapse_remap(psi, e, np.full(32, 0.9), np.full(32, 0.9 * s))
+        assert np.all(flags == 0) and np.all(out >= 0.0)
+
+
 def gauss_mean(f, lo, hi):
     x, w = np.polynomial.legendre.leggauss(4)
     t = 0.5 * (hi - lo) * x[:, None] + 0.5 * (hi + lo)

@@ -39,9 +39,15 @@ def flags():
     ]
 
 
+# Per-source extra flags.  The coupled-block elimination is a fully unrolled loop over up to 57 pivot
+# steps (a run-time step index would index the register-held row and move it to scratch); its size
+# exceeds the default limit of `#pragma unroll`, and a partly unrolled loop spills to scratch memory.
+EXTRA = {"tm_ye.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *flags(), *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

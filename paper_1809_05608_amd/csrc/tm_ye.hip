@@ -152,7 +152,7 @@ struct alignas(16) YeLds {
     double yr[2 * NT];         // Y_e row entries, one per species row
     double ys[2 * NT];         // species terms of dG_Y/dY_e
     double fix[MT][MT + 1];    // row-ownership fix-up after pivoting
-    int sidx[64];              // elimination step at which lane r was the pivot row
+    int plane[MT];             // pivot lane of each elimination step
 };
 
 template <int NT>
@@ -206,10 +206,16 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
     double* ws = A.ws + (size_t)rb * I * (NC + 1) * MT;                // zone i: C [NC][MT], then y [MT]
 
     // ---------------------------------------------------------------- forward sweep
-    double a[MT];
+    // L.fix holds, between zones, the rows of C_{i-1} (columns [0, MT)) and y_{i-1} (column MT) in natural
+    // order.  Each zone: (1) every lane turns its row of that matrix into its row of
+    // Ahat_i = A_i - diag(bm_i) C_{i-1} in place (storing C_{i-1}, y_{i-1} to the workspace on the way), so
+    // no register-held row is live during the assembly; (2) the row is loaded into registers for the
+    // elimination; (3) the eliminated rows go back to L.fix in natural order.
+    if (is_row) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m) a[m] = 0.0;
-    double ycar = 0.0;
+        for (int m = 0; m <= MT; ++m) L.fix[kr][m] = 0.0;
+    }
+    double* frow = L.fix[kr];
     double psi_c = real ? psi[kk] : 0.0;
     double sig_c = real ? ka[kk] + et[kk] : 0.0;
     double lam_c = real ? drcp(sig_c + ks[kk]) : 1.0;
@@ -217,6 +223,10 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
     bool zp = false;
 
     for (int i = 0; i < I; ++i) {
+        // lane and group indices re-materialised per zone: comparisons with them are evaluated where used
+        // instead of being hoisted out of the zone loop as dozens of live lane masks
+        int lz = lane, kz = k;
+        asm volatile("" : "+v"(lz), "+v"(kz));
         double psi_n1 = 0.0, sig_n1 = 0.0, lam_n1 = 1.0;
         if (i + 1 < I && real) {
             const size_t cn = (size_t)(i + 1) * N + kk;
@@ -250,19 +260,15 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
         // Y_e terms of the zone (eq. a62ad: Y_e column of the species rows; eq. a62a: the Y_e row)
         const double dy = A.ye[zb + i] - A.y.ye_n[zb + i];
         const double z = ye_zeta(A.y.rho[zb + i]);
-        double ycol = 0.0;
+        double ycol = 0.0, yrow = 0.0, ysum = 0.0;
         if (emabs && real) {
             const double dk = dka[(size_t)i * N + kk], de = det[(size_t)i * N + kk];
             diag += c * dy * (dk + de);
             ycol = c * (dk * psi_c - de * (1.0 - psi_c));
-            if (lane < NC) {
-                L.yr[lane] = -sgn * c * z * Wk * (sig_c + dy * (dk + de));
-                L.ys[lane] = sgn * Wk * (de * (1.0 - psi_c) - dk * psi_c);
-            }
-        } else if (lane < NC) {
-            L.yr[lane] = 0.0;
-            L.ys[lane] = 0.0;
+            yrow = -sgn * c * z * Wk * (sig_c + dy * (dk + de));
+            ysum = sgn * Wk * (de * (1.0 - psi_c) - dk * psi_c);
         }
+        ysum = wave_sum(ysum);
         double amp = 0.0;
         if (nes) {
             amp = az[i];
@@ -272,123 +278,143 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
         }
         wave_sync();
 
-        // ---- row of Ahat_i = A_i - diag(bm_i) C_{i-1}
+        // ---- (1) row of Ahat_i in LDS
+        double nrow[NT];                               // NES entries of the lane's own species block
 #pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = real ? -bm * a[m] : 0.0;
+        for (int kp = 0; kp < NT; ++kp) nrow[kp] = 0.0;
         if (nes && real) {
-            // NES part of the species block: -c dt [(1 - psi_k) K^in_{kk'} + psi_k K^out_{kk'}], placed in
-            // the columns of the lane's own species; its diagonal sums go to diag
+            // -c dt [(1 - psi_k) K^in_{kk'} + psi_k K^out_{kk'}]; the diagonal sums go to diag
             const double ca = -c * amp;
             const double cap = ca * psi_c, cam = ca * (1.0 - psi_c);
             const double* pq = L.bc + (q0 ? 0 : NT);
             double er = 1.0, so = 0.0, si = 0.0;
 #pragma unroll
             for (int kp = 0; kp < NT; ++kp) {
-                if (kp > 0) er = (kp > k) ? er * L.dd[kp - 1] : 1.0;
+                if (kp > 0) er = (kp > kz) ? er * L.dd[kp - 1] : 1.0;
                 const double po = Prow[kp] * er;
                 so = fma(po, 1.0 - pq[kp], so);
-                const double v = cap * po;
-                a[kp] = q0 ? a[kp] + v : a[kp];
-                a[NT + kp] = q0 ? a[NT + kp] : a[NT + kp] + v;
+                nrow[kp] = cap * po;
             }
             double el = 1.0;
 #pragma unroll
             for (int kp = NT - 1; kp >= 0; --kp) {
-                el = (kp < k) ? el * L.dd[kp] : 1.0;
+                el = (kp < kz) ? el * L.dd[kp] : 1.0;
                 const double pi = Prow[kp] * el;
                 si = fma(pi, pq[kp], si);
-                const double v = cam * pi;
-                a[kp] = q0 ? a[kp] + v : a[kp];
-                a[NT + kp] = q0 ? a[NT + kp] : a[NT + kp] + v;
+                nrow[kp] = fma(cam, pi, nrow[kp]);
             }
             diag += c * amp * (si + so);
+        }
+        double ycar = 0.0;
+        if (is_row) {
+            ycar = frow[MT];
+            if (i > 0) {                               // C_{i-1}, y_{i-1} to the workspace
+                double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + lane;
+#pragma unroll
+                for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = frow[m];
+                wz[(size_t)NC * MT] = ycar;
+            }
         }
         if (real) {
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
-                if (m < NC) a[m] += (m == lane) ? diag : 0.0;
-                else a[m] += ycol;
+                double v = -bm * frow[m];
+                if (m < NT) v += q0 ? nrow[m] : 0.0;
+                else if (m < NC) v += q0 ? 0.0 : nrow[m - NT];
+                v += (m == lz) ? diag : 0.0;
+                if (m == NC) v += ycol;
+                frow[m] = v;
             }
-        } else if (isY) {
-            double s = 0.0;
+        } else if (lane < NC) {
 #pragma unroll
-            for (int m = 0; m < NC; ++m) {
-                a[m] = L.yr[m];
-                s += L.ys[m];
-            }
-            a[NC] = emabs ? 1.0 + c * z * s : 1.0;
-        } else {
-#pragma unroll
-            for (int m = 0; m < MT; ++m) a[m] = (m == lane) ? 1.0 : 0.0;    // padded identity row
+            for (int m = 0; m < MT; ++m) frow[m] = (m == lz) ? 1.0 : 0.0;     // padded identity row
         }
+        wave_sync();
+        // the Y_e row: one entry from every species lane, the diagonal from the sum over them
+        if (lane < NC) L.fix[NC][lane] = yrow;
+        if (isY) L.fix[NC][NC] = emabs ? 1.0 + c * z * ysum : 1.0;
+        wave_sync();
+
+        // ---- (2) elimination in registers
+        double a[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = is_row ? frow[m] : 0.0;
         double g = 0.0;
         if (real) g = fma(-bm, ycar, A.rhs_sign * rhs[(size_t)i * N + kk]);
         else if (isY) g = A.rhs_sign * A.GY[zb + i];
         const double bcoef = bp;
 
-        // ---- in-place Gauss-Jordan on [Ahat | diag(bp) | g], partial pivoting over the wavefront
-        bool used = !is_row;
+        // in-place Gauss-Jordan on [Ahat | diag(bp) | g], partial pivoting over the wavefront
+        // (the step loop must be fully unrolled: a[cc] with a run-time cc would put the row in scratch)
+        int used = is_row ? 0 : 1;
         double mypiv = 1.0;
         int mycol = 0;
 #pragma unroll
         for (int cc = 0; cc < MT; ++cc) {
             const double ac = a[cc];
-            const uint32_t key = used ? 0u : ((abs_key_bits(ac) & ~63u) | (uint32_t)(63 - lane));
+            const uint32_t key = used ? 0u : ((abs_key_bits(ac) & ~63u) | (uint32_t)(63 - lz));
             uint32_t km = group_max<32>(key);
             km = max((uint32_t)__builtin_amdgcn_readlane((int)km, 0), (uint32_t)__builtin_amdgcn_readlane((int)km, 32));
             const int p = 63 - (int)(km & 63u);
-            const bool isp = lane == p;
+            const bool isp = lz == p;
             if (isp) {
 #pragma unroll
                 for (int j = 0; j < MT; ++j) L.prow[j] = a[j];
                 L.prow[MT] = g;
                 L.prow[MT + 1] = bcoef;
+                L.plane[cc] = lane;
             }
             wave_sync();
-            const double piv = L.prow[cc];
-            zp |= !(piv != 0.0);
+            // the whole pivot row is read before it is used, so its LDS reads are issued back to back and
+            // waited for once (one LDS latency per step instead of one per few columns)
+            double pr[MT + 2];
+#pragma unroll
+            for (int j = 0; j < MT + 2; ++j) pr[j] = L.prow[j];
+#pragma unroll
+            for (int j = 0; j < MT + 2; ++j) asm volatile("" : "+v"(pr[j]));
+            const double piv = pr[cc];
             const double pinv = drcp(piv);
             const double fm = isp ? 0.0 : ac * pinv;
 #pragma unroll
             for (int j = 0; j < MT; ++j)
-                if (j != cc) a[j] = fma(-fm, L.prow[j], a[j]);
-            g = fma(-fm, L.prow[MT], g);
-            const double bpiv = L.prow[MT + 1];
+                if (j != cc) a[j] = fma(-fm, pr[j], a[j]);
+            g = fma(-fm, pr[MT], g);
+            const double bpiv = pr[MT + 1];
             a[cc] = isp ? bpiv : -fm * bpiv;
-            if (isp) {
-                used = true;
-                mypiv = piv;
-                mycol = cc;
-            }
+            // kept current in every step: left alone, the compiler defers these selects to the end of the
+            // zone and holds every step's pivot and lane mask until then
+            used |= isp ? 1 : 0;
+            mypiv = isp ? piv : mypiv;
+            mycol = isp ? cc : mycol;
+            asm volatile("" : "+v"(used), "+v"(mypiv), "+v"(mycol));
             wave_sync();
         }
-        // restore row ownership: the lane holding unknown mycol writes its scaled row; slot sidx[m] (the
-        // step at which lane m was the pivot) holds column m of C
+        // every pivot is some row's own pivot: a zero one is seen here, once per zone
+        zp |= is_row && !(mypiv != 0.0);
+
+        // ---- (3) restore row ownership: the lane holding unknown mycol writes its scaled row, slot cc (which
+        //      holds the column of C of the step's pivot lane plane[cc]) going to that column, so rows and
+        //      columns come back in natural order
         if (is_row) {
             const double ip = drcp(mypiv);
+            double* dst = L.fix[mycol];
 #pragma unroll
-            for (int cc = 0; cc < MT; ++cc) L.fix[mycol][cc] = a[cc] * ip;
-            L.fix[mycol][MT] = g * ip;
-            L.sidx[lane] = mycol;
+            for (int cc = 0; cc < MT; ++cc) dst[L.plane[cc]] = a[cc] * ip;
+            dst[MT] = g * ip;
         }
         wave_sync();
-#pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = is_row ? L.fix[kr][L.sidx[m]] : 0.0;
-        ycar = is_row ? L.fix[kr][MT] : 0.0;
-        wave_sync();
-
-        if (is_row) {
-            double* wz = ws + (size_t)i * (NC + 1) * MT + lane;
-#pragma unroll
-            for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = a[m];
-            wz[(size_t)NC * MT] = ycar;
-        }
 
         psi_c = psi_n1;
         sig_c = sig_n1;
         lam_c = lam_n1;
         dHu_lo = dHu_hi;
         dHv_lo = dHv_hi;
+    }
+    if (is_row) {                                      // C_{I-1}, y_{I-1}
+        double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + lane;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = frow[m];
+        wz[(size_t)NC * MT] = frow[MT];
     }
 
     // ---------------------------------------------------------------- backward sweep
@@ -429,8 +455,9 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
         for (int m = 0; m < NC; ++m) cr[m] = crn[m];
         yv = yn;
     }
+    const bool any_zp = __ballot(zp) != 0ull;
     if (lane == 0) {
-        if (zp && A.flags) A.flags[ray] |= 4;
+        if (any_zp && A.flags) A.flags[ray] |= 4;
         A.iters[ray] += 1;
         A.pending[ray] = 1;                    // trial psi + delta awaits the line search
         A.alpha[ray] = 1.0;

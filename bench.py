@@ -59,9 +59,9 @@ def source_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_record(kernel_src):
+def traffic_record(kernel_src, record="k_factor_traffic.json"):
     """HBM traffic per launch measured with rocprofv3 --pmc, if taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_factor_traffic.json")
+    path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -260,9 +260,12 @@ def energy_leg(tm, torch, synth, w, rays, reps):
     torch.cuda.empty_cache()
     cells, zones = w.n_cells, w.R * w.I
     b = energy_bytes(cells, zones)
+    # counters taken on the full 16384-ray launch; a reduced run reports none
+    tr = traffic_record(os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_energy.hip"),
+                        "k_energy_advect_traffic.json") if rays is None else None
     return dict(kernel="k_energy_advect<20>", kernel_ms=1e3 * t, cells_per_s=cells / t,
                 zone_updates_per_s=w.S * zones / t, algorithmic_bytes_per_launch=b, achieved_gbs=b / t / 1e9,
-                hbm_frac=b / t / 1e9 / PEAK_HBM_GBS)
+                hbm_frac=b / t / 1e9 / PEAK_HBM_GBS, traffic=(tr or {}).get("bytes_per_launch"))
 
 
 def cpu_baseline(sample_systems: int, workers: int):
@@ -298,6 +301,73 @@ def cpu_baseline(sample_systems: int, workers: int):
                 os.environ[k] = v
     upd = sum(it for it in res) * w["I"] * w["N"]
     return upd / dt, dt, len(jobs), upd
+
+
+def _pool_map(fn, args, workers):
+    """Map `fn` over `args` on `workers` single-threaded spawned processes; returns (results, wall s)."""
+    import multiprocessing as mp
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            pool.map(_noop, range(workers))            # interpreter start-up outside the timed region
+            t0 = time.perf_counter()
+            res = pool.map(fn, args, chunksize=1)
+            dt = time.perf_counter() - t0
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return res, dt
+
+
+def cpu_baseline_ye(sample_rays: int, workers: int):
+    """The Y_e-coupled oracle (FP64 Newton to the same rule) on `sample_rays` rays of the workload."""
+    import synth
+    rays = list(range(0, 16384, 16384 // sample_rays))[:sample_rays]
+    w = synth.make(4, rays=rays, device="cpu")
+    y = synth.ye_inputs(w, 4, rays=rays)
+    wn, yn = w.numpy(), y.numpy()
+    args = [({k: (v[:, r:r + 1] if k in ("kappa_a", "eta", "kappa_s", "psi_n", "nes_amp") else
+                  v[r:r + 1] if k in ("r_edge", "temp") else v) for k, v in wn.items()},
+             {k: (v[:, r:r + 1] if k in ("dka_dye", "deta_dye") else v[r:r + 1]) for k, v in yn.items()})
+            for r in range(len(rays))]
+    for a in args:
+        a[0].update(R=1)
+    res, dt = _pool_map(_ye_oracle_one, args, workers)
+    upd = sum(res) * 2 * w.I * w.N
+    return dict(value=upd / dt, unit="updates/s (nu_e and anti-nu_e cells)", cores=workers, kind="oracle",
+                sample=f"{len(rays)} rays of the workload, coupled FP64 Newton to 1e-12, {sum(res)} block "
+                       f"updates in {dt:.1f} s wall")
+
+
+def _ye_oracle_one(a):
+    from oracle import ye_coupled as yc
+    wn, yn = a
+    cs = yc.coupled_systems(wn, yn)[0]
+    u_n = yc.pack(wn["psi_n"][0, 0], wn["psi_n"][1, 0], cs.ye_n)
+    return yc.newton(cs, u_n, max_iter=30, rtol=1e-12).iters
+
+
+def cpu_baseline_energy(sample_rays: int):
+    """The energy-advection oracle (vectorised NumPy, one process) on `sample_rays` rays of the workload."""
+    import synth
+    from oracle import energy_advection as ea
+    rays = list(range(0, 16384, 16384 // sample_rays))[:sample_rays]
+    w = synth.make(4, rays=rays, device="cpu")
+    e = synth.eadv_inputs(w, 4, rays=rays)
+    wn, en = w.numpy(), e.numpy()
+    t0 = time.perf_counter()
+    ea.energy_advect(wn["psi_n"], wn["e_edge"], rho_old=en["rho_old"], rho_new=en["rho_new"], a_old=en["lapse_old"],
+                     a_new=en["lapse_new"], dlnR=en["dlnR"], dlnb=en["dlnb"], eddington=en["eddington"])
+    dt = time.perf_counter() - t0
+    cells = wn["psi_n"].size
+    return dict(value=cells / dt, unit="cells/s", cores=1, kind="oracle",
+                sample=f"{len(rays)} rays x 540 zones x 4 species ({cells // w.N} zones) of the workload in "
+                       f"{dt:.1f} s")
 
 
 def _noop(_):
@@ -446,6 +516,11 @@ def main(argv=None):
         cpu = dict(value=v, unit="updates/s", cores=workers, kind="oracle",
                    sample=f"{nsys} systems (species x rays spread over the 16384 rays) of the same workload, "
                           f"FP64 Newton to 1e-12, {upd} updates in {dt:.1f} s wall")
+        if out_ye is not None:
+            log("CPU oracle baseline of the Y_e-coupled step")
+            out_ye["cpu_oracle"] = cpu_baseline_ye(16, workers)
+        log("CPU oracle baseline of the energy advection")
+        out_energy["cpu_oracle"] = cpu_baseline_energy(16)
 
     res = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps,

@@ -468,62 +468,104 @@ template <int NT>
 __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts* __restrict__ cs,
                                                 const double* __restrict__ psi, const double* __restrict__ mu,
                                                 double* g_ka, double* g_eta, double* g_ks, double* g_amp) {
+    // one block per system, one thread per cell: rows of NT threads are zones, so a wave's loads of a
+    // cell array (and of the neighbouring zones' cells) are contiguous
+    constexpr int RZ = kBlock / NT;             // zones per chunk
+    constexpr int PS = NT + 1;                  // padded LDS row stride
+    __shared__ double s_P[NT * PS];
+    __shared__ double s_p[RZ][PS];              // the zone's psi row
+    __shared__ double s_d[RZ][PS];              // neighbour detailed-balance factors exp(-(eps_k+1 - eps_k)/T)
+    __shared__ double s_m[RZ][PS];              // mu_k c dt
+    __shared__ double s_s[RZ][PS];              // (1 - psi_k) S^in_k - psi_k S^out_k
     const long long sys = blockIdx.x;
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
     const double* re = f.r_edge + (size_t)ray * (I + 1);
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
-    for (int i = threadIdx.x; i < I; i += kBlock) {
-        const size_t cb = ((size_t)sys * I + i) * N;
-        const ZoneGeom g = zone_geom(re, i, I);
-        double p[NT];
-#pragma unroll
-        for (int k = 0; k < NT; ++k) p[k] = k < N ? psi[cb + k] : 0.0;
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (k >= N) break;
-            const double lam = inv_mfp(f, cb + k);
-            const double m0 = mu[cb + k];
+    const bool amp = g_amp != nullptr;
+    const int t = threadIdx.x, zl = t / NT, k = t - zl * NT;
+    const bool tile = zl < RZ;
+    const bool lane_ok = tile && k < N;
+    if (amp && nes)
+        for (int j = t; j < NT * NT; j += kBlock) s_P[(j / NT) * PS + (j % NT)] = cs->P[j / NT][j % NT];
+
+    for (int z0 = 0; z0 < I; z0 += RZ) {
+        const int i = z0 + zl;
+        const bool in_zone = lane_ok && i < I;
+        const size_t cb = ((size_t)sys * I + (in_zone ? i : 0)) * N + (in_zone ? k : 0);
+        double pk = 0.0, m0 = 0.0;
+        if (in_zone) {
+            const ZoneGeom g = zone_geom(re, i, I);
+            pk = psi[cb];
+            m0 = mu[cb];
+            const double lam = inv_mfp(f, cb);
             double gchi = 0.0;     // sum over the two edges of (mu-weighted dG/dH) dH/dlam dlam/dchi
             if (diff) {
                 if (i + 1 < I) {
-                    const size_t cp = cb + N + k;
+                    const size_t cp = cb + N;
                     const double lam_e = sqrt(lam * inv_mfp(f, cp));
-                    const EdgeFlux e = edge_flux(p[k], psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter);
+                    const EdgeFlux e = edge_flux(pk, psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter);
                     const double w = c * g.A_hi * (m0 / g.V - mu[cp] / g.V_hi);
                     gchi += w * e.dHlam * (-0.5 * lam_e * lam);
                 }
                 if (i > 0) {
-                    const size_t cm = cb - N + k;
+                    const size_t cm = cb - N;
                     const double lam_e = sqrt(lam * inv_mfp(f, cm));
-                    const EdgeFlux e = edge_flux(psi[cm], p[k], lam_e, g.D_lo, sh.psi_floor, sh.limiter);
+                    const EdgeFlux e = edge_flux(psi[cm], pk, lam_e, g.D_lo, sh.psi_floor, sh.limiter);
                     const double w = c * g.A_lo * (mu[cm] / g.V_lo - m0 / g.V);
                     gchi += w * e.dHlam * (-0.5 * lam_e * lam);
                 }
             }
             double gka = gchi, geta = gchi;
             if (emabs) {
-                gka += m0 * c * p[k];
-                geta -= m0 * c * (1.0 - p[k]);
+                gka += m0 * c * pk;
+                geta -= m0 * c * (1.0 - pk);
             }
-            if (g_ka) g_ka[cb + k] = -gka;
-            if (g_eta) g_eta[cb + k] = -geta;
-            if (g_ks) g_ks[cb + k] = -gchi;
+            if (g_ka) g_ka[cb] = -gka;
+            if (g_eta) g_eta[cb] = -geta;
+            if (g_ks) g_ks[cb] = -gchi;
         }
-        if (g_amp) {
-            double ga = 0.0;
-            if (nes) {
-                double si[NT], so[NT];
-                nes_zone<NT>(cs, N, f.temp[(size_t)ray * I + i], p, si, so);
-#pragma unroll
-                for (int k = 0; k < NT; ++k) {
-                    if (k >= N) break;
-                    const double s1 = (1.0 - p[k]) * si[k] - p[k] * so[k];
-                    ga = fma(mu[cb + k] * c, s1, ga);
-                }
+        if (!amp) continue;
+        if (nes) {
+            // sum_k mu_k c [(1 - psi_k) S^in_k - psi_k S^out_k] over each zone (the NES source of the zone,
+            // Phi_0 terms of eq. d8, differentiated with respect to its amplitude)
+            __syncthreads();                                // previous chunk done with the rows
+            if (tile) {
+                s_p[zl][k] = pk;
+                s_d[zl][k] = (in_zone && k + 1 < N) ? exp(-cs->de[k] / f.temp[(size_t)ray * I + i]) : 0.0;
             }
-            g_amp[(size_t)sys * I + i] = ga;
+            __syncthreads();
+            double s1 = 0.0;
+            if (in_zone) {
+                double sin_ = 0.0, sout = 0.0, e = 1.0;
+                for (int kp = k + 1; kp < N; ++kp) {        // up-scatter side: out factor decays
+                    e *= s_d[zl][kp - 1];
+                    const double pp = s_p[zl][kp], P = s_P[k * PS + kp];
+                    sout = fma(P * e, 1.0 - pp, sout);
+                    sin_ = fma(P, pp, sin_);
+                }
+                e = 1.0;
+                for (int kp = k - 1; kp >= 0; --kp) {       // down-scatter side: in factor decays
+                    e *= s_d[zl][kp];
+                    const double pp = s_p[zl][kp], P = s_P[k * PS + kp];
+                    sin_ = fma(P * e, pp, sin_);
+                    sout = fma(P, 1.0 - pp, sout);
+                }
+                s1 = (1.0 - pk) * sin_ - pk * sout;
+            }
+            if (tile) {
+                s_m[zl][k] = m0 * c;
+                s_s[zl][k] = s1;
+            }
+            __syncthreads();
+            if (tile && k == 0 && i < I) {
+                double ga = 0.0;
+                for (int kk = 0; kk < N; ++kk) ga = fma(s_m[zl][kk], s_s[zl][kk], ga);
+                g_amp[(size_t)sys * I + i] = ga;
+            }
+        } else if (tile && k == 0 && i < I) {
+            g_amp[(size_t)sys * I + i] = 0.0;
         }
     }
 }

@@ -63,6 +63,8 @@ class System:
     terms: int = 7
     limiter: int = 1
     psi_floor: float = 1e-300
+    lapse: Optional[np.ndarray] = None        # [I] lapse a_i at zone centres (None: a = 1)
+    lapse_edge: Optional[np.ndarray] = None   # [I+1] lapse at zone edges
 
     @property
     def I(self) -> int:
@@ -84,7 +86,9 @@ def systems_from_workload(w: dict) -> List[List[System]]:
                 kappa_a=w["kappa_a"][s, r], eta=w["eta"][s, r], kappa_s=w["kappa_s"][s, r],
                 nes_amp=w["nes_amp"][s, r], nes_g=w["nes_g"], c_dt=w["c_dt"],
                 inner_bc=w["inner_bc"], outer_bc=w["outer_bc"], terms=w["terms"],
-                limiter=w["limiter"], psi_floor=w["psi_floor"]))
+                limiter=w["limiter"], psi_floor=w["psi_floor"],
+                lapse=w["lapse"][r] if w.get("lapse") is not None else None,
+                lapse_edge=w["lapse_edge"][r] if w.get("lapse_edge") is not None else None))
         out.append(row)
     return out
 
@@ -161,6 +165,28 @@ def edge_flux(u, v, lam, D, floor, limiter=1):
     return H, dH_du, dH_dv, dH_dlam
 
 
+def lapse_factors(sys: System):
+    """Lapse at zone centres a_i [I] and edges a_{i+1/2} [I+1] (ones without a lapse).
+
+    With a lapse, eq. a58 times a_i c dt puts a_i^3 / V_i in front of the flux difference, the edge
+    areas become A_{i+1/2} / a_{i+1/2}^2, and the emission/absorption and NES sources carry a_i.  The
+    energy grid e_edge then holds energies at infinity E (eq. a8a): a zone's groups sit at the local
+    energies E / a_i, at which the opacities are given and the NES kernels evaluated."""
+    I = sys.kappa_a.shape[0]
+    a = np.ones(I) if sys.lapse is None else np.asarray(sys.lapse, dtype=np.float64)
+    ae = np.ones(I + 1) if sys.lapse_edge is None else np.asarray(sys.lapse_edge, dtype=np.float64)
+    if (sys.lapse is None) != (sys.lapse_edge is None):
+        raise ValueError("lapse and lapse_edge go together")
+    return a, ae
+
+
+def _weights(sys: System):
+    """Per-zone factor a_i^3 / V_i of the flux difference and per-edge areas A / a^2 (eq. a58)."""
+    _, V, A, _ = geometry(sys.r_edge)
+    a, ae = lapse_factors(sys)
+    return a ** 3 / V, A / ae ** 2, a
+
+
 def _lambda(sys: System):
     return 1.0 / (sys.kappa_a + sys.eta + sys.kappa_s)
 
@@ -187,13 +213,15 @@ def _edge_fluxes(sys: System, psi: np.ndarray):
 
 
 def nes_source(sys: System, psi: np.ndarray, unit_amplitude: bool = False):
-    """S_{i,k}: zeroth moment of the NES collision term (eq. d8, Phi_0 terms; eq. d40)."""
+    """S_{i,k}: zeroth moment of the NES collision term (eq. d8, Phi_0 terms; eq. d40), with the kernels
+    at the zone's local energies (E / a_i with a lapse)."""
     I, N = psi.shape
     eps, W = group_energies(sys.e_edge)
+    a, _ = lapse_factors(sys)
     S = np.zeros((I, N))
     for i in range(I):
         amp = 1.0 if unit_amplitude else sys.nes_amp[i]
-        k_out, k_in = _off_diagonal(*nes_kernels(amp, sys.temp[i], eps, W, sys.nes_g))
+        k_out, k_in = _off_diagonal(*nes_kernels(amp, sys.temp[i], eps / a[i], W, sys.nes_g))
         p = psi[i]
         S[i] = (1.0 - p) * (k_in @ p) - p * (k_out @ (1.0 - p))
     return S
@@ -214,20 +242,20 @@ def _off_diagonal(*kernels):
 # ---------------------------------------------------------------- residual and Jacobian
 
 def residual(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> np.ndarray:
-    """G(psi) = c*dt times eq. a58 (lapse 1), per cell [I][N].
+    """G(psi) = a_i c dt times eq. a58, per cell [I][N] (a = 1 without a lapse).
 
-    G_{i,k} = psi - psi^n + c dt { (A_{i+1/2} H_{i+1/2} - A_{i-1/2} H_{i-1/2}) / V_i
-                                   - eta (1 - psi) + kappa_a psi - S_{i,k} }
+    G_{i,k} = psi - psi^n + c dt { a_i^3 (A_{i+1/2} H_{i+1/2} / a_{i+1/2}^2 - A_{i-1/2} H_{i-1/2} / a_{i-1/2}^2) / V_i
+                                   + a_i [ - eta (1 - psi) + kappa_a psi - S_{i,k} ] }
     """
-    _, V, A, _ = geometry(sys.r_edge)
+    vf, Aw, a = _weights(sys)
     G = psi - psi_n
     if sys.terms & TERM_DIFFUSION:
         H = _edge_fluxes(sys, psi)[0]
-        G = G + sys.c_dt * (A[1:, None] * H[1:] - A[:-1, None] * H[:-1]) / V[:, None]
+        G = G + sys.c_dt * (Aw[1:, None] * H[1:] - Aw[:-1, None] * H[:-1]) * vf[:, None]
     if sys.terms & TERM_EMABS:
-        G = G + sys.c_dt * (-sys.eta * (1.0 - psi) + sys.kappa_a * psi)
+        G = G + sys.c_dt * a[:, None] * (-sys.eta * (1.0 - psi) + sys.kappa_a * psi)
     if sys.terms & TERM_NES:
-        G = G - sys.c_dt * nes_source(sys, psi)
+        G = G - sys.c_dt * a[:, None] * nes_source(sys, psi)
     return G
 
 
@@ -238,7 +266,7 @@ def jacobian_blocks(sys: System, psi: np.ndarray):
     off-diagonal blocks coupling zone i to zones i-1 and i+1).
     """
     I, N = psi.shape
-    _, V, Aed, _ = geometry(sys.r_edge)
+    vf, Aed, a = _weights(sys)
     eps, W = group_energies(sys.e_edge)
     c = sys.c_dt
     blocks = np.zeros((I, N, N))
@@ -249,22 +277,23 @@ def jacobian_blocks(sys: System, psi: np.ndarray):
         _, dHu, dHv, _, _ = _edge_fluxes(sys, psi)
         for i in range(I):
             # G_i contains +A_{i+1/2} H_{i+1/2}(psi_i, psi_{i+1}) - A_{i-1/2} H_{i-1/2}(psi_{i-1}, psi_i)
-            diag[i] += c * (Aed[i + 1] * dHu[i + 1] - Aed[i] * dHv[i]) / V[i]
+            diag[i] += c * (Aed[i + 1] * dHu[i + 1] - Aed[i] * dHv[i]) * vf[i]
             if i + 1 < I:
-                bp[i] = c * Aed[i + 1] * dHv[i + 1] / V[i]
+                bp[i] = c * Aed[i + 1] * dHv[i + 1] * vf[i]
             if i > 0:
-                bm[i] = -c * Aed[i] * dHu[i] / V[i]
+                bm[i] = -c * Aed[i] * dHu[i] * vf[i]
     if sys.terms & TERM_EMABS:
-        diag += c * (sys.eta + sys.kappa_a)
+        diag += c * a[:, None] * (sys.eta + sys.kappa_a)
     for i in range(I):
         blocks[i][np.diag_indices(N)] = diag[i]
         if sys.terms & TERM_NES:
-            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g))
+            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps / a[i], W, sys.nes_g))
             p = psi[i]
-            # -c dS_k/dpsi_m : dense part for every m (the m = k term included) ...
-            blocks[i] -= c * ((1.0 - p)[:, None] * k_in + p[:, None] * k_out)
+            ca = c * a[i]
+            # -c a dS_k/dpsi_m : dense part for every m (the m = k term included) ...
+            blocks[i] -= ca * ((1.0 - p)[:, None] * k_in + p[:, None] * k_out)
             # ... plus the diagonal derivative through the explicit (1 - psi_k), psi_k factors
-            blocks[i][np.diag_indices(N)] += c * (k_in @ p + k_out @ (1.0 - p))
+            blocks[i][np.diag_indices(N)] += ca * (k_in @ p + k_out @ (1.0 - p))
     return blocks, bm, bp
 
 
@@ -400,25 +429,25 @@ def residual_rounding_level(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> 
     ulp moves G by about |dG/dpsi| ulp(psi); below this level the computed residual is
     rounding, so the stopping rule asks for no progress beyond it.
     """
-    _, V, A, _ = geometry(sys.r_edge)
+    vf, A, a = _weights(sys)
     c = sys.c_dt
     mag = np.abs(psi) + np.abs(psi_n)
     jd = np.ones_like(psi)              # bound of |dG_ik/dpsi_ik|
     if sys.terms & TERM_DIFFUSION:
         H, dHu, dHv, _, _ = _edge_fluxes(sys, psi)
-        mag = mag + c * (np.abs(A[1:, None] * H[1:]) + np.abs(A[:-1, None] * H[:-1])) / V[:, None]
-        jd = jd + c * (A[1:, None] * np.abs(dHu[1:]) + A[:-1, None] * np.abs(dHv[:-1])) / V[:, None]
+        mag = mag + c * (np.abs(A[1:, None] * H[1:]) + np.abs(A[:-1, None] * H[:-1])) * vf[:, None]
+        jd = jd + c * (A[1:, None] * np.abs(dHu[1:]) + A[:-1, None] * np.abs(dHv[:-1])) * vf[:, None]
     if sys.terms & TERM_EMABS:
-        mag = mag + c * (np.abs(sys.kappa_a * psi) + np.abs(sys.eta * (1.0 - psi)))
-        jd = jd + c * (sys.kappa_a + sys.eta)
+        mag = mag + c * a[:, None] * (np.abs(sys.kappa_a * psi) + np.abs(sys.eta * (1.0 - psi)))
+        jd = jd + c * a[:, None] * (sys.kappa_a + sys.eta)
     if sys.terms & TERM_NES:
         eps, W = group_energies(sys.e_edge)
         for i in range(psi.shape[0]):
-            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps, W, sys.nes_g))
+            k_out, k_in = _off_diagonal(*nes_kernels(sys.nes_amp[i], sys.temp[i], eps / a[i], W, sys.nes_g))
             p = psi[i]
             si, so = k_in @ p, k_out @ (1.0 - p)
-            mag[i] += c * (np.abs(1.0 - p) * np.abs(si) + np.abs(p) * np.abs(so))
-            jd[i] += c * (np.abs(si) + np.abs(so))
+            mag[i] += c * a[i] * (np.abs(1.0 - p) * np.abs(si) + np.abs(p) * np.abs(so))
+            jd[i] += c * a[i] * (np.abs(si) + np.abs(so))
     mag = mag + np.abs(psi) * jd
     return 32.0 * np.finfo(np.float64).eps * float(np.max(mag))
 
@@ -435,16 +464,19 @@ def step_stats(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> dict:
     b_n     = c dt A_{I+1/2} sum_k W_k H_{I+1/2,k}     (number through the outer surface)
     budget  = n_tot - n_tot^n + b_n - q_n - nes_n    (equals sum V W G)
     lum_n   = c A_{I+1/2} sum_k W_k H_{I+1/2,k}        (number luminosity, 4pi and (hc)^-3 dropped)
+    With a lapse, V_i becomes V_i / a_i^3 (the local phase-space weight is W / a^3), A_{I+1/2} becomes
+    A_{I+1/2} / a_{I+1/2}^2, the sources carry a_i, and e_tot is the energy at infinity (E = a eps).
     """
-    _, V, A, _ = geometry(sys.r_edge)
+    vf, A, a = _weights(sys)
     eps, W = group_energies(sys.e_edge)
     I, N = psi.shape
-    VW = V[:, None] * W[None, :]
+    VW = (1.0 / vf)[:, None] * W[None, :]
     n_tot = float(np.sum(VW * psi))
     n_old = float(np.sum(VW * psi_n))
     e_tot = float(np.sum(VW * eps[None, :] * psi))
-    q_n = float(sys.c_dt * np.sum(VW * (sys.eta * (1.0 - psi) - sys.kappa_a * psi))) if sys.terms & TERM_EMABS else 0.0
-    nes_n = float(sys.c_dt * np.sum(VW * nes_source(sys, psi))) if sys.terms & TERM_NES else 0.0
+    q_n = float(sys.c_dt * np.sum(VW * a[:, None] * (sys.eta * (1.0 - psi) - sys.kappa_a * psi))) \
+        if sys.terms & TERM_EMABS else 0.0
+    nes_n = float(sys.c_dt * np.sum(VW * a[:, None] * nes_source(sys, psi))) if sys.terms & TERM_NES else 0.0
     if sys.terms & TERM_DIFFUSION and sys.outer_bc == 1:
         h_out = psi[I - 1]
     else:
@@ -456,8 +488,9 @@ def step_stats(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> dict:
 
 
 def luminosity(sys: System, psi: np.ndarray) -> float:
-    """L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}: number leaving the outer surface per unit time (eq. a62)."""
-    _, _, A, _ = geometry(sys.r_edge)
+    """L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}: number leaving the outer surface per unit time (eq. a62;
+    with a lapse A_{I+1/2} / a_{I+1/2}^2)."""
+    _, A, _ = _weights(sys)
     _, W = group_energies(sys.e_edge)
     I = psi.shape[0]
     if not (sys.terms & TERM_DIFFUSION) or sys.outer_bc != 1:
@@ -467,7 +500,7 @@ def luminosity(sys: System, psi: np.ndarray) -> float:
 
 def luminosity_seed(sys: System, shape) -> np.ndarray:
     """dL_N/dpsi as a cell array: nonzero only in the outermost zone."""
-    _, _, A, _ = geometry(sys.r_edge)
+    _, A, _ = _weights(sys)
     _, W = group_energies(sys.e_edge)
     I, N = shape
     seed = np.zeros((I, N))
@@ -492,6 +525,8 @@ def param_vjp(sys: System, psi: np.ndarray, mu: np.ndarray) -> dict:
     with d lambda_e / d chi_i = -lambda_e lambda_i / 2 for chi = 1/lambda;
     dG/d amp_i = -c dt S_{i,k}/amp_i; dG/dpsi^n = -1.
     """
+    if sys.lapse is not None:
+        raise NotImplementedError("the parameter VJP is written for a = 1 (the device adjoint takes no lapse)")
     I, N = psi.shape
     _, V, A, _ = geometry(sys.r_edge)
     c = sys.c_dt

@@ -495,7 +495,7 @@ def main(argv=None):
     achieved = bytes_launch / t_fac / 1e9
     roof = dict(bound="hbm" if t_hbm >= t_alu else "alu", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=achieved / PEAK_HBM_GBS, traffic=(tr or {}).get("bytes_per_launch"),
-                kernel="k_factor<float,20,false>", kernel_ms=1e3 * t_fac,
+                kernel="k_factor_f32<20>", kernel_ms=1e3 * t_fac,
                 algorithmic_bytes_per_launch=bytes_launch, flops_per_launch=flops_launch,
                 alu_tflops=flops_launch / t_fac / 1e12, alu_peak_tflops=PEAK_VALU_TFLOPS,
                 roofline_ms=1e3 * max(t_hbm, t_alu), residual_kernel_ms=1e3 * t_res)

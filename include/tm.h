@@ -119,7 +119,20 @@ typedef struct {
     const double *temp;     /* zone, MeV (> 0), used by the NES detailed balance          */
     const double *nes_amp;  /* sysz, cm^-1; may be NULL when TM_TERM_NES is off          */
     const double *nes_g;    /* [N][N] symmetric shape; may be NULL when TM_TERM_NES is off */
+    const double *lapse;    /* zone [R][I], lapse a_i at zone centres (> 0); NULL: a = 1       */
+    const double *lapse_edge; /* edge [R][I+1], lapse at zone edges; given with lapse or not at all */
 } tm_inputs;
+
+/* The lapse (eq. a58 with a != 1; eq. a8a).  With `lapse` set, the residual is a_i c dt times eq. a58:
+ *   G_{i,k} = psi - psi^n + c dt { a_i^3 (A_{i+1/2} H_{i+1/2} / a_{i+1/2}^2 - A_{i-1/2} H_{i-1/2} / a_{i-1/2}^2) / V_i
+ *                                  + a_i [ - eta (1 - psi) + kappa_a psi - S_{i,k} ] },
+ * e_edge holds energies at infinity E, the groups of zone i sit at the local energies E / a_i (at which
+ * the caller gives kappa_a, eta, kappa_s), and the NES kernels are evaluated at those local energies.
+ * The statistics become: number sum_i V_i / a_i^3 sum_k W_k psi, energy at infinity with the same
+ * weights, outer flux c A_{I+1/2} / a_{I+1/2}^2 sum_k W_k H.  tm_assemble, tm_factor_solve and
+ * tm_newton_step take a lapse (the library keeps lapse-folded copies of kappa_a, eta, kappa_s, temp and
+ * nes_amp: three cell arrays of workspace); tm_adjoint_step, tm_luminosity_seed, tm_ye_newton_step and
+ * tm_temperature_update return TM_ERR_INVALID_ARG when one is given. */
 
 typedef struct {            /* every array is per system [S][R], device memory        */
     double  *res_inf;       /* max |G| at the returned psi                              */

@@ -61,6 +61,12 @@ struct tm_ctx {
     int* y_flags = nullptr;
     int* y_pending = nullptr;
     int* y_backtrack = nullptr;
+    // inputs with the lapse folded in (allocated on first use with a lapse)
+    double* lp_ka = nullptr;
+    double* lp_et = nullptr;
+    double* lp_ks = nullptr;
+    double* lp_temp = nullptr;   // [R][I]
+    double* lp_amp = nullptr;    // [S][R][I]
 };
 
 namespace {
@@ -109,6 +115,8 @@ tmk::Fields fields_of(const tm_inputs& in) {
     f.kappa_s = in.kappa_s;
     f.temp = in.temp;
     f.nes_amp = in.nes_amp;
+    f.lapse = in.lapse;
+    f.lapse_edge = in.lapse_edge;
     return f;
 }
 
@@ -135,6 +143,35 @@ tm_status check_inputs(tm_ctx* c, const tm_inputs* in, bool need_opacity = true)
         return set_err(c, TM_ERR_INVALID_ARG, "kappa_a, eta and kappa_s are required");
     if ((c->p.terms & TM_TERM_NES) && (!in->nes_amp || !in->nes_g || !in->temp))
         return set_err(c, TM_ERR_INVALID_ARG, "nes_amp, nes_g and temp are required when TM_TERM_NES is on");
+    if (!in->lapse != !in->lapse_edge) return set_err(c, TM_ERR_INVALID_ARG, "lapse and lapse_edge go together");
+    return TM_OK;
+}
+
+tm_status no_lapse(tm_ctx* c, const tm_inputs* in, const char* what) {
+    if (in && in->lapse) return set_err(c, TM_ERR_INVALID_ARG, std::string(what) + " takes no lapse (lapse must be NULL)");
+    return TM_OK;
+}
+
+// Inputs with the lapse's source factor folded in (see k_lapse_fold); `out` is `*in` without a lapse.
+tm_status fold_lapse(tm_ctx* c, const tm_inputs* in, tm_inputs* out) {
+    *out = *in;
+    if (!in->lapse) return TM_OK;
+    const size_t cells = (size_t)n_cells(c->p) * sizeof(double);
+    const size_t zones = (size_t)c->p.n_rays * c->p.n_zones * sizeof(double);
+    const size_t sysz = (size_t)n_systems(c->p) * c->p.n_zones * sizeof(double);
+    TM_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+    for (double** p : {&c->lp_ka, &c->lp_et, &c->lp_ks})
+        if (!*p) TM_TRY(hip_check(c, hipMalloc((void**)p, cells), "hipMalloc lapse-folded inputs"));
+    if (!c->lp_temp) TM_TRY(hip_check(c, hipMalloc((void**)&c->lp_temp, zones), "hipMalloc lapse-folded inputs"));
+    if (!c->lp_amp) TM_TRY(hip_check(c, hipMalloc((void**)&c->lp_amp, sysz), "hipMalloc lapse-folded inputs"));
+    TM_TRY(hip_check(c, tmk::launch_lapse_fold(shape_of(c->p), in->lapse, in->kappa_a, in->eta, in->kappa_s, in->temp,
+                                               in->nes_amp, c->lp_ka, c->lp_et, c->lp_ks, c->lp_temp, c->lp_amp,
+                                               c->stream), "lapse folding kernel"));
+    out->kappa_a = c->lp_ka;
+    out->eta = c->lp_et;
+    out->kappa_s = c->lp_ks;
+    if (in->temp) out->temp = c->lp_temp;
+    if (in->nes_amp) out->nes_amp = c->lp_amp;
     return TM_OK;
 }
 
@@ -402,6 +439,8 @@ tm_status tm_destroy(tm_ctx* c) {
             (void)hipFree(p);
         for (int* p : {c->y_active, c->y_iters, c->y_flags, c->y_pending, c->y_backtrack}) (void)hipFree(p);
     }
+    for (double* p : {c->lp_ka, c->lp_et, c->lp_ks, c->lp_temp, c->lp_amp})
+        if (p) (void)hipFree(p);
     if (c->gbuf) (void)hipFree(c->gbuf);
     if (c->dbuf) (void)hipFree(c->dbuf);
     if (c->ws && c->ws_owned) (void)hipFree(c->ws);
@@ -437,6 +476,9 @@ tm_status tm_assemble(tm_ctx* c, const tm_inputs* in, const double* psi_n, const
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     if (!psi_n || !psi || !residual) return set_err(c, TM_ERR_INVALID_ARG, "psi_n, psi and residual are required");
+    tm_inputs folded;
+    TM_TRY(fold_lapse(c, in, &folded));
+    in = &folded;
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     const tmk::Fields f = fields_of(*in);
@@ -456,6 +498,9 @@ tm_status tm_factor_solve(tm_ctx* c, const tm_inputs* in, const double* psi, con
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     if (!psi || !rhs || !x) return set_err(c, TM_ERR_INVALID_ARG, "psi, rhs and x are required");
+    tm_inputs folded;
+    TM_TRY(fold_lapse(c, in, &folded));
+    in = &folded;
     TM_TRY(ensure_small(c));
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, c->p.n_groups, c->consts, c->stream),
                      "setup kernel"));
@@ -473,6 +518,9 @@ tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, do
     TM_TRY(check_inputs(c, in));
     if (!psi_n || !psi) return set_err(c, TM_ERR_INVALID_ARG, "psi_n and psi are required");
     if (max_iter < 0 || !(rtol >= 0.0)) return set_err(c, TM_ERR_INVALID_ARG, "max_iter >= 0 and rtol >= 0 required");
+    tm_inputs folded;
+    TM_TRY(fold_lapse(c, in, &folded));
+    in = &folded;
     TM_TRY(ensure_small(c));
     TM_TRY(ensure_gbuf(c));
     const long long ns = n_systems(c->p);
@@ -569,6 +617,7 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     if (!psi_np1 || !seed || !mu) return set_err(c, TM_ERR_INVALID_ARG, "psi_np1, seed and mu are required");
+    TM_TRY(no_lapse(c, in, "the adjoint step"));
     (void)psi_n;
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
@@ -594,6 +643,7 @@ tm_status tm_ye_newton_step(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* 
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     TM_TRY(check_ye_inputs(c, yin));
+    TM_TRY(no_lapse(c, in, "the Y_e-coupled step"));
     if (c->p.precision != TM_PREC_FP64)
         return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step is FP64 only (precision must be TM_PREC_FP64)");
     if (!psi_n || !psi || !ye) return set_err(c, TM_ERR_INVALID_ARG, "psi_n, psi and ye are required");
@@ -719,6 +769,7 @@ tm_status tm_temperature_update(tm_ctx* c, const tm_inputs* in, const tm_ye_inpu
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     TM_TRY(check_ye_inputs(c, yin));
+    TM_TRY(no_lapse(c, in, "the temperature update"));
     if (!in->temp) return set_err(c, TM_ERR_INVALID_ARG, "temp (T^n) is required");
     if (!psi || !ye || !stat_weights || !de_dT || !de_dye || !temp_out)
         return set_err(c, TM_ERR_INVALID_ARG, "psi, ye, stat_weights, de_dT, de_dye and temp_out are required");
@@ -769,6 +820,7 @@ tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, 
     if (!c) return TM_ERR_INVALID_ARG;
     if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
     if (!seed) return set_err(c, TM_ERR_INVALID_ARG, "seed is required");
+    TM_TRY(no_lapse(c, in, "the luminosity seed (the adjoint path)"));
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));

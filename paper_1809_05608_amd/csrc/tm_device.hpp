@@ -42,7 +42,22 @@ struct Fields {
     const double* kappa_s;
     const double* temp;     // [R][I]
     const double* nes_amp;  // [S][R][I]
+    const double* lapse;        // [R][I] lapse at zone centres, or nullptr (a = 1)
+    const double* lapse_edge;   // [R][I+1] lapse at zone edges (set together with lapse)
 };
+
+// Lapse factors of eq. a58 times a_i c dt: the flux difference of zone i carries a_i^3 / V_i and the
+// area of edge e becomes A_e / a_e^2 (the sources' factor a_i is folded into the inputs by the host).
+__device__ __forceinline__ double lapse_zone3(const Fields& f, size_t zone) {
+    if (!f.lapse) return 1.0;
+    const double a = f.lapse[zone];
+    return a * a * a;
+}
+__device__ __forceinline__ double lapse_edge_inv2(const Fields& f, size_t edge) {
+    if (!f.lapse_edge) return 1.0;
+    const double a = f.lapse_edge[edge];
+    return 1.0 / (a * a);
+}
 
 constexpr unsigned kDiffusion = 1u, kEmAbs = 2u, kNes = 4u;
 

@@ -19,6 +19,8 @@
 // and either writes x or adds it to psi (Newton update, eq. a62aa).
 // The transposed variant (adjoint) assembles the same rows, transposes the block
 // through LDS and swaps the roles of bm and bp.
+#include <type_traits>
+
 #include "tm_kernels.hpp"
 
 namespace tmk {
@@ -83,8 +85,8 @@ struct alignas(16) SysLds {
 template <int NT, bool PIVOT>
 constexpr int lanes_per_system() { return PIVOT ? (NT > 16 ? 32 : 16) : NT; }
 
-template <typename T, int NT, bool TRANS, bool PIVOT>
-__global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
+template <typename T, int NT, bool TRANS, bool PIVOT, bool LAPSE = true>
+__device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     constexpr int SL = lanes_per_system<NT, PIVOT>();
     constexpr int SPW = 64 / SL;
     constexpr int SPB = (kBlock / 64) * SPW;
@@ -171,8 +173,21 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
         }
         const double rlo = re[i], rhi = re[i + 1];
         const double V = shell_volume(rlo, rhi);
-        const double iV = rcp_nr(V);
-        const double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double iV = rcp_nr(V);
+        double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double lap_hi = 1.0;
+        if (LAPSE && A.f.lapse) {                           // eq. a58 times a_i c dt: a^3 / V and A / a^2
+            const double* lz = A.f.lapse + (size_t)ray * I;
+            const double* le = A.f.lapse_edge + (size_t)ray * (I + 1);
+            const double a0 = lz[i], e0 = le[i], e1 = le[i + 1];
+            iV *= a0 * a0 * a0;
+            A_lo /= e0 * e0;
+            A_hi /= e1 * e1;
+            if (i + 1 < I) {
+                const double a1 = lz[i + 1];
+                lap_hi = a1 * a1 * a1;
+            }
+        }
         double dHu_hi = 0.0, dHv_hi = 0.0, V_hi = 1.0;
         if (i + 1 < I) {
             const double rp = re[i + 2];
@@ -191,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
             diag += c * (A_hi * dHu_hi - A_lo * dHv_lo) * iV;
             if (i + 1 < I) bp = c * A_hi * dHv_hi * iV;
             if (i > 0) bm = -c * A_lo * dHu_lo * iV;
-            if (i + 1 < I) bm_next = -c * A_hi * dHu_hi * rcp_nr(V_hi);
+            if (i + 1 < I) bm_next = -c * A_hi * dHu_hi * rcp_nr(V_hi) * lap_hi;
         }
         if (emabs) diag += c * sig_c;
 
@@ -484,12 +499,29 @@ size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
     return (size_t)I * NT * (NT + 1) * es;
 }
 
+template <typename T, int NT, bool TRANS, bool PIVOT>
+__global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
+    factor_sweeps<T, NT, TRANS, PIVOT>(A);
+}
+
+// The float32 forward kernel with diagonal pivots (the mixed-precision Newton update) held to 128 VGPRs,
+// four waves per SIMD: it fits without spilling, and left alone the compiler settles a few registers
+// above the limit and runs three.
+template <int NT, bool LAPSE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_factor_f32(FactorArgs A) {
+    factor_sweeps<float, NT, false, false, LAPSE>(A);
+}
+
 template <typename T, int NT, bool TR, bool PV>
 static void launch_t(const FactorArgs& a, hipStream_t st) {
     constexpr int SL = lanes_per_system<NT, PV>();
     constexpr int SPB = (kBlock / 64) * (64 / SL);
     const long long blocks = (a.nsys + SPB - 1) / SPB;
-    hipLaunchKernelGGL((k_factor<T, NT, TR, PV>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+    if constexpr (std::is_same<T, float>::value && !TR && !PV && NT <= 20) {
+        if (a.f.lapse) hipLaunchKernelGGL((k_factor_f32<NT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_factor_f32<NT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+    } else
+        hipLaunchKernelGGL((k_factor<T, NT, TR, PV>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
 }
 
 template <typename T, int NT>

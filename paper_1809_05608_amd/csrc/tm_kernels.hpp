@@ -164,6 +164,11 @@ hipError_t launch_ye_temperature(const Shape& sh, const Fields& f, const YeField
 size_t ye_ws_bytes_per_ray(int I, int N);
 constexpr int kYeMaxGroups = 28;          // 2 NT + 1 rows of a coupled block fit one wavefront
 
+// Lapse folded into the inputs (source factor a, NES at local energies); writes the folded copies.
+hipError_t launch_lapse_fold(const Shape& sh, const double* lapse, const double* ka, const double* et,
+                             const double* ks, const double* temp, const double* amp, double* oka, double* oet,
+                             double* oks, double* otemp, double* oamp, hipStream_t st);
+
 // Energy advection (eqs. a78-a81d) and lapse remap (eqs. p1-p8), one thread per (species, ray, zone).
 constexpr int kEaLagrangian = 0, kEaLapse = 1;                            // TM_EADV_* modes
 constexpr int kEaDisplacement = 1, kEaOverfill = 2, kEaOverfillClamp = 4;  // TM_EADV_FLAG_* bits

@@ -4,6 +4,8 @@
 // Mapping: one 256-thread block per (species, ray) system; each thread owns whole
 // radial zones (strided), computes all N groups of a zone in registers, and the block
 // reduces per-system quantities in a fixed order (deterministic, no atomics).
+#include <algorithm>
+
 #include "tm_kernels.hpp"
 
 namespace tmk {
@@ -88,12 +90,15 @@ struct ZoneGeom {
     double V, A_lo, A_hi, D_lo, D_hi, V_lo, V_hi;
 };
 
-__device__ __forceinline__ ZoneGeom zone_geom(const double* __restrict__ re, int i, int I) {
+// Geometry of zone i of a ray; with a lapse (f.lapse set) the volumes are V / a^3 and the areas A / a^2.
+__device__ __forceinline__ ZoneGeom zone_geom(const double* __restrict__ re, int i, int I, const Fields& f,
+                                              int ray) {
     ZoneGeom g;
     const double rlo = re[i], rhi = re[i + 1];
-    g.V = shell_volume(rlo, rhi);
-    g.A_lo = rlo * rlo;
-    g.A_hi = rhi * rhi;
+    const size_t z = (size_t)ray * I + i, e = (size_t)ray * (I + 1) + i;
+    g.V = shell_volume(rlo, rhi) / lapse_zone3(f, z);
+    g.A_lo = rlo * rlo * lapse_edge_inv2(f, e);
+    g.A_hi = rhi * rhi * lapse_edge_inv2(f, e + 1);
     const double rc = 0.5 * (rlo + rhi);
     g.D_lo = 0.0;
     g.V_lo = 1.0;
@@ -102,12 +107,12 @@ __device__ __forceinline__ ZoneGeom zone_geom(const double* __restrict__ re, int
     if (i > 0) {
         const double rm = re[i - 1];
         g.D_lo = rc - 0.5 * (rm + rlo);
-        g.V_lo = shell_volume(rm, rlo);
+        g.V_lo = shell_volume(rm, rlo) / lapse_zone3(f, z - 1);
     }
     if (i + 1 < I) {
         const double rp = re[i + 2];
         g.D_hi = 0.5 * (rhi + rp) - rc;
-        g.V_hi = shell_volume(rhi, rp);
+        g.V_hi = shell_volume(rhi, rp) / lapse_zone3(f, z + 1);
     }
     return g;
 }
@@ -131,7 +136,7 @@ __device__ __forceinline__ double inv_mfp(const Fields& f, size_t c) {
 // kernel computes the rounding level of G (32 ulp of the largest per-cell sum of term
 // magnitudes plus |psi| |dG/dpsi|), below which the Newton stopping rule does not ask for
 // further progress.
-template <int NT>
+template <int NT, bool LAPSE>
 __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const Consts* __restrict__ cs,
                                                      const double* __restrict__ psi_n,
                                                      const double* __restrict__ psi, double* __restrict__ G_out,
@@ -266,11 +271,18 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         double G = p - pn;
         double scale = fabs(p) + fabs(pn);
         const double rlo = s_re[zl], rhi = s_re[zl + 1];
-        const double V = shell_volume(rlo, rhi);
+        double V = shell_volume(rlo, rhi);
+        double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        if (LAPSE && f.lapse) {                             // eq. a58 times a_i c dt: V / a^3 and A / a^2
+            const double a0 = f.lapse[(size_t)ray * I + i];
+            const double e0 = f.lapse_edge[(size_t)ray * (I + 1) + i], e1 = f.lapse_edge[(size_t)ray * (I + 1) + i + 1];
+            V /= a0 * a0 * a0;
+            A_lo /= e0 * e0;
+            A_hi /= e1 * e1;
+        }
         double Hh = 0.0;
         double jd = 1.0;                                    // |dG_ik/dpsi_ik| bound, for the rounding level
         if (diff) {
-            const double A_lo = rlo * rlo, A_hi = rhi * rhi;
             const double Hlo = s_H[zl - 1][k], dlo = s_dv[zl - 1][k];
             Hh = s_H[zl][k];
             const double dhi = s_du[zl][k];
@@ -376,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
             }
         }
         if (out.stats) {
-            const double rout = re[I] * re[I];
+            const double rout = re[I] * re[I] * (LAPSE ? lapse_edge_inv2(f, (size_t)ray * (I + 1) + I) : 1.0);
             const double b = c * rout * s_b;
             if (out.n_tot) out.n_tot[sys] = s_n;
             if (out.e_tot) out.e_tot[sys] = s_e;
@@ -398,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_blocks(Shape sh, Fields f, const Con
     const double c = sh.c_dt;
     for (int i = threadIdx.x; i < I; i += kBlock) {
         const size_t cb = ((size_t)sys * I + i) * N;
-        const ZoneGeom g = zone_geom(re, i, I);
+        const ZoneGeom g = zone_geom(re, i, I, f, ray);
         double p[NT];
 #pragma unroll
         for (int k = 0; k < NT; ++k) p[k] = k < N ? psi[cb + k] : 0.0;
@@ -496,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
         const size_t cb = ((size_t)sys * I + (in_zone ? i : 0)) * N + (in_zone ? k : 0);
         double pk = 0.0, m0 = 0.0;
         if (in_zone) {
-            const ZoneGeom g = zone_geom(re, i, I);
+            const ZoneGeom g = zone_geom(re, i, I, f, ray);
             pk = psi[cb];
             m0 = mu[cb];
             const double lam = inv_mfp(f, cb);
@@ -568,6 +580,46 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
             g_amp[(size_t)sys * I + i] = 0.0;
         }
     }
+}
+
+// ---------------------------------------------------------------- lapse folding
+
+// With a lapse the emission/absorption and NES sources of eq. a58 (times a_i c dt) carry a_i, and the NES
+// kernels are evaluated at the local energies E / a_i.  Both are exact transformations of the inputs:
+// kappa_a -> a kappa_a and eta -> a eta, with kappa_s -> kappa_s + (1 - a)(kappa_a + eta) so that the
+// transport mean free path 1/(kappa_a + eta + kappa_s) is unchanged; the NES kernel's energy factor
+// eps_k eps_k' / eps0^2 becomes 1/a^2 of its value at infinity and its exponent (eps_k' - eps_k)/T becomes
+// (eps_k' - eps_k)/(a T), so amp -> amp / a (with the source's a) and T -> a T.
+__global__ __launch_bounds__(kBlock) void k_lapse_fold(long long ncell, int N, long long RI, long long nsz,
+                                                       const double* __restrict__ lapse,
+                                                       const double* __restrict__ ka, const double* __restrict__ et,
+                                                       const double* __restrict__ ks, const double* __restrict__ temp,
+                                                       const double* __restrict__ amp, double* __restrict__ oka,
+                                                       double* __restrict__ oet, double* __restrict__ oks,
+                                                       double* __restrict__ otemp, double* __restrict__ oamp) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += stride) {
+        const double a = lapse[(c / N) % RI];
+        const double k_a = ka[c], e = et[c];
+        oka[c] = a * k_a;
+        oet[c] = a * e;
+        oks[c] = ks[c] + (1.0 - a) * (k_a + e);
+    }
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nsz; j += stride) {
+        const long long z = j % RI;
+        if (amp) oamp[j] = amp[j] / lapse[z];
+        if (temp && j < RI) otemp[j] = lapse[j] * temp[j];
+    }
+}
+
+hipError_t launch_lapse_fold(const Shape& sh, const double* lapse, const double* ka, const double* et,
+                             const double* ks, const double* temp, const double* amp, double* oka, double* oet,
+                             double* oks, double* otemp, double* oamp, hipStream_t st) {
+    const long long RI = (long long)sh.R * sh.I, nsz = (long long)sh.S * RI, ncell = nsz * sh.N;
+    const long long blocks = std::min<long long>((ncell + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_lapse_fold, dim3((unsigned)blocks), dim3(kBlock), 0, st, ncell, sh.N, RI, nsz, lapse, ka, et,
+                       ks, temp, amp, oka, oet, oks, otemp, oamp);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- luminosity seed
@@ -725,9 +777,15 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
                            const double* psi, double* G_out, double g_sign, const ResidualOut& out,
                            hipStream_t st) {
     const long long nsys = (long long)sh.S * sh.R;
-    TM_DISPATCH_NT(padded_groups(sh.N),
-                   hipLaunchKernelGGL(k_residual<NT>, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f, cs,
-                                      psi_n, psi, G_out, g_sign, out));
+    if (f.lapse) {
+        TM_DISPATCH_NT(padded_groups(sh.N),
+                       hipLaunchKernelGGL((k_residual<NT, true>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f,
+                                          cs, psi_n, psi, G_out, g_sign, out));
+    } else {
+        TM_DISPATCH_NT(padded_groups(sh.N),
+                       hipLaunchKernelGGL((k_residual<NT, false>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f,
+                                          cs, psi_n, psi, G_out, g_sign, out));
+    }
     return hipGetLastError();
 }
 

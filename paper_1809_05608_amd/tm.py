@@ -47,7 +47,7 @@ class Problem(ctypes.Structure):
 
 class Inputs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
-                ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp", "nes_amp", "nes_g")]
+                ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp", "nes_amp", "nes_g", "lapse", "lapse_edge")]
 
 
 class Stats(ctypes.Structure):
@@ -134,6 +134,8 @@ class DeviceFields:
     temp: torch.Tensor
     nes_amp: torch.Tensor
     nes_g: torch.Tensor
+    lapse: Optional[torch.Tensor] = None        # [R][I] lapse at zone centres (None: a = 1)
+    lapse_edge: Optional[torch.Tensor] = None   # [R][I+1] lapse at zone edges
 
     @classmethod
     def of(cls, w, **override):
@@ -196,6 +198,10 @@ class Context:
         exp = {"r_edge": (p.n_rays, p.n_zones + 1), "e_edge": (p.n_groups + 1,), "kappa_a": self.shape_cell,
                "eta": self.shape_cell, "kappa_s": self.shape_cell, "temp": (p.n_rays, p.n_zones),
                "nes_amp": (p.n_species, p.n_rays, p.n_zones), "nes_g": (p.n_groups, p.n_groups)}
+        if (f.lapse is None) != (f.lapse_edge is None):
+            raise ValueError("lapse and lapse_edge go together")
+        if f.lapse is not None:
+            exp.update(lapse=(p.n_rays, p.n_zones), lapse_edge=(p.n_rays, p.n_zones + 1))
         for name, shape in exp.items():
             t = getattr(f, name)
             if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous():
@@ -204,7 +210,7 @@ class Context:
                 raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
         self._keep = f
         return Inputs(*[_ptr(getattr(f, n)) for n in ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp",
-                                                       "nes_amp", "nes_g")])
+                                                       "nes_amp", "nes_g", "lapse", "lapse_edge")])
 
     def set_workspace(self, nbytes: int):
         """Give the context a caller-owned workspace of `nbytes` (a torch uint8 tensor)."""

@@ -1,0 +1,164 @@
+"""Parity of the transport step with a lapse (eq. a58 with a != 1) against the oracle, through the C ABI,
+and the static gravitational-redshift test (eqs. t1-t7) on the GPU."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import transport as tr
+from paper_1809_05608_amd import tm
+
+pytestmark = pytest.mark.gpu
+TAU = 1e-30
+R0 = 5.0e5          # cm: a(R) = sqrt(1 - R0 / R), 0.71 at the inner edge of the grids used here
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, ref):
+    return float(np.max(np.abs(a - ref) / np.maximum(np.abs(ref), TAU)))
+
+
+def lapse_of(w):
+    re = w.r_edge.cpu().numpy()
+    rc = 0.5 * (re[:, 1:] + re[:, :-1])
+    return np.sqrt(1.0 - R0 / rc), np.sqrt(1.0 - R0 / re)
+
+
+def setup(w, precision=tm.PREC_FP64):
+    a, ae = lapse_of(w)
+    wn = w.numpy()
+    wn["lapse"], wn["lapse_edge"] = a, ae
+    wd = w.to("cuda")
+    f = tm.DeviceFields.of(wd, lapse=torch.as_tensor(a, device="cuda"), lapse_edge=torch.as_tensor(ae, device="cuda"))
+    return wn, wd, f, tm.Context(tm.problem_of(wd, precision))
+
+
+SHAPES = [dict(S=1, R=8, I=64, N=12), dict(S=2, R=3, I=37, N=13), dict(S=1, R=5, I=19, N=20), dict(S=1, R=2, I=2, N=5)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_residual_and_blocks_with_lapse_match_oracle(shape):
+    say("case lapse residual/blocks", shape)
+    w = synth.make_custom(**shape)
+    wn, wd, f, ctx = setup(w)
+    rng = np.random.default_rng(21)
+    psi = (wn["psi_n"] * rng.uniform(0.7, 1.3, wn["psi_n"].shape)).clip(0, 1)
+    psi_d = torch.as_tensor(psi, device="cuda")
+    G = torch.empty_like(psi_d)
+    B = torch.empty(tuple(psi_d.shape) + (w.N + 2,), dtype=torch.float64, device="cuda")
+    ctx.assemble(f, wd.psi_n, psi_d, G, B)
+    torch.cuda.synchronize()
+    G, B = G.cpu().numpy(), B.cpu().numpy()
+    syss = oracle.systems_from_workload(wn)
+    for s in range(w.S):
+        for r in range(w.R):
+            Go = oracle.residual(syss[s][r], wn["psi_n"][s, r], psi[s, r])
+            np.testing.assert_allclose(G[s, r], Go, rtol=1e-11, atol=1e-13)
+            A, bm, bp = oracle.jacobian_blocks(syss[s][r], psi[s, r])
+            scale = np.max(np.abs(A), axis=2, keepdims=True)
+            np.testing.assert_allclose(B[s, r, :, :, :w.N], A, rtol=0, atol=1e-12 * scale.max())
+            np.testing.assert_allclose(B[s, r, :, :, w.N], bm, rtol=1e-11, atol=1e-14 * scale.max())
+            np.testing.assert_allclose(B[s, r, :, :, w.N + 1], bp, rtol=1e-11, atol=1e-14 * scale.max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,rtol,bar", [(tm.PREC_FP64, 0.0, 1e-12), (tm.PREC_FP64, 1e-10, 1e-12),
+                                                (tm.PREC_MIXED, 1e-12, 1e-8)])
+@pytest.mark.parametrize("shape", SHAPES[:3])
+def test_newton_with_lapse_matches_oracle(shape, precision, rtol, bar):
+    say("case lapse newton", shape, precision, rtol)
+    w = synth.make_custom(**shape)
+    wn, wd, f, ctx = setup(w, precision)
+    psi = wd.psi_n.clone()
+    max_iter = 3 if rtol == 0.0 else 30
+    st, stats = ctx.newton_step(f, wd.psi_n, psi, max_iter, rtol, raise_on_status=False)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy()
+    ref, info = oracle.newton_batch(wn, max_iter=max_iter, rtol=rtol if precision == tm.PREC_FP64 else 1e-12)
+    err = rel_err(got, ref)
+    iters = stats["iters"].cpu().numpy()
+    say(f"  err {err:.3e} status {tm.STATUS_NAMES[st]} iters {iters.ravel().tolist()[:8]}")
+    assert st == 0 and err <= bar
+    if precision == tm.PREC_FP64:
+        assert iters.ravel().tolist() == [info[(s, r)].iters for s in range(w.S) for r in range(w.R)]
+    # conservation statistics with the lapse weights against the oracle
+    syss = oracle.systems_from_workload(wn)
+    for s in range(w.S):
+        for r in range(w.R):
+            o = oracle.step_stats(syss[s][r], wn["psi_n"][s, r], ref[s, r])
+            j = s * w.R + r
+            assert stats["n_tot"][j].item() == pytest.approx(o["n_tot"], rel=1e-11)
+            assert stats["e_tot"][j].item() == pytest.approx(o["e_tot"], rel=1e-11)
+            assert stats["lum_n"][j].item() == pytest.approx(o["lum_n"], rel=1e-11, abs=1e-300)
+            assert abs(stats["budget_n"][j].item() - o["budget"]) <= 1e-9 * abs(o["n_tot"])
+    ctx.close()
+
+
+def test_static_redshift_on_the_gpu():
+    """An emitting core inside a transparent, static medium with a(R) = sqrt(1 - R0/R), stepped to its
+    steady state: the flux at infinity A H / a^2 of every group is the same at every edge (eq. t3), the
+    local luminosity goes as a^-2 (eq. t4) and the flux-mean local energy as a^-1 (eq. t7)."""
+    say("case lapse static redshift")
+    I, N = 40, 8
+    w = synth.make_custom(S=1, R=1, I=I, N=N)
+    r_edge = 1e6 * 100.0 ** (np.arange(I + 1) / I)
+    rc = 0.5 * (r_edge[1:] + r_edge[:-1])
+    eps, _ = tr.group_energies(w.e_edge.numpy())
+    a = np.sqrt(1.0 - R0 / rc)
+    T = 8.0 * (r_edge[:-1] / 1e6) ** -0.3
+    loc = eps[None, :] / a[:, None]
+    ka = 1e-5 * (loc / 10.0) ** 2
+    eta = ka * np.exp(-(loc - 2.0 * T[:, None]) / T[:, None])
+    ks = 2.0 * ka
+    ka[4:], eta[4:], ks[4:] = 0.0, 0.0, 1e-14
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64)
+    w = dataclasses.replace(w, r_edge=t(r_edge[None]), temp=t(T[None]), kappa_a=t(ka[None, None]),
+                            eta=t(eta[None, None]), kappa_s=t(ks[None, None]), psi_n=t(np.zeros((1, 1, I, N))),
+                            c_dt=1e22, terms=tm.TERM_DIFFUSION | tm.TERM_EMABS)
+    wn, wd, f, ctx = setup(w)
+    psi = wd.psi_n.clone()
+    st, stats = ctx.newton_step(f, wd.psi_n, psi, 80, 1e-15, raise_on_status=False)
+    torch.cuda.synchronize()
+    psi = psi.cpu().numpy()[0, 0]
+    sysm = oracle.systems_from_workload(wn)[0][0]
+    H = tr._edge_fluxes(sysm, psi)[0]
+    _, _, A, _ = tr.geometry(r_edge)
+    ae = wn["lapse_edge"][0]
+    edges = np.arange(6, I)
+    phi = A[edges, None] * H[edges] / ae[edges, None] ** 2
+    say(f"  status {tm.STATUS_NAMES[st]} iters {int(stats['iters'].max())} flux spread "
+        f"{np.max(np.abs(phi / phi[0] - 1.0)):.2e}")
+    assert np.all(phi > 0.0) and np.allclose(phi, phi[0][None, :], rtol=1e-9, atol=0)
+    lum = A[edges] * np.sum((eps / ae[edges, None]) * H[edges] * np.diff(w.e_edge.numpy() ** 3) / 3.0
+                            / ae[edges, None] ** 3, axis=1)
+    assert np.allclose(lum * ae[edges] ** 2, (lum * ae[edges] ** 2)[0], rtol=1e-9, atol=0)
+    _, W = tr.group_energies(w.e_edge.numpy())
+    mean_e = np.sum(W * (eps / ae[edges, None]) * H[edges], axis=1) / np.sum(W * H[edges], axis=1)
+    assert np.allclose(mean_e * ae[edges], (mean_e * ae[edges])[0], rtol=1e-9, atol=0)
+    ctx.close()
+
+
+def test_lapse_is_rejected_where_it_is_not_supported():
+    say("case lapse rejected")
+    w = synth.make_custom(S=2, R=2, I=8, N=6)
+    wn, wd, f, ctx = setup(w)
+    psi = wd.psi_n.clone()
+    mu = torch.empty_like(psi)
+    with pytest.raises(tm.TMError, match="INVALID_ARG"):
+        ctx.adjoint_step(f, wd.psi_n, psi, psi, mu)
+    with pytest.raises(tm.TMError, match="INVALID_ARG"):
+        ctx.luminosity_seed(f, mu)
+    y = synth.ye_inputs(wd, 0, R_full=w.R)
+    with pytest.raises(tm.TMError, match="INVALID_ARG"):
+        ctx.ye_newton_step(f, y, wd.psi_n, psi, y.ye_n.clone(), 3, 0.0)
+    with pytest.raises(ValueError):
+        ctx.assemble(dataclasses.replace(f, lapse_edge=None), wd.psi_n, psi, torch.empty_like(psi))
+    ctx.close()

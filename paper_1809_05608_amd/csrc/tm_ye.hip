@@ -158,8 +158,12 @@ struct alignas(16) YeLds {
 template <int NT>
 constexpr int ye_waves_per_block() { return NT <= 20 ? 4 : 2; }
 
+// waves per SIMD the register allocation is held to: two up to 20 groups (256 VGPRs, no scratch), one above
 template <int NT>
-__global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
+constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
+
+template <int NT, int WEU>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) void k_ye_factor(YeFactorArgs A) {
     constexpr int MT = 2 * NT + 1;              // rows of a coupled block (<= 57)
     constexpr int NC = 2 * NT;                  // columns of C that can be non-zero (Y_e has bp = 0)
     constexpr int WPB = ye_waves_per_block<NT>();
@@ -169,7 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
     for (int j = threadIdx.x; j < NT * NT; j += blockDim.x) s_P[(j / NT) * PS + (j % NT)] = A.cs->P[j / NT][j % NT];
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: ray addressing stays scalar
     const long long rb = (long long)blockIdx.x * WPB + wave;           // ray within the batch
     if (rb >= A.nray) return;                                          // whole wave (no block barrier follows)
     const long long ray = A.ray0 + rb;
@@ -216,6 +221,15 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
         for (int m = 0; m <= MT; ++m) L.fix[kr][m] = 0.0;
     }
     double* frow = L.fix[kr];
+    // NES neighbour factors exp(-(eps_{j+1} - eps_j)/T) of every zone, computed before the sweep by lane j and
+    // parked in the first row of the zone's workspace slot: the sweep reads them back in that zone and the same
+    // lane overwrites them with C only in the next zone.  Out of the zone loop, the exponential's constants do not
+    // stay live across the elimination.
+    if (nes && lane < NT) {
+        const double dej = lane + 1 < N ? A.cs->de[lane] : 0.0;
+        for (int i = 0; i < I; ++i)
+            ws[(size_t)i * (NC + 1) * MT + lane] = (lane + 1 < N) ? exp(-dej / tz[i]) : 0.0;
+    }
     double psi_c = real ? psi[kk] : 0.0;
     double sig_c = real ? ka[kk] + et[kk] : 0.0;
     double lam_c = real ? drcp(sig_c + ks[kk]) : 1.0;
@@ -272,9 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
         double amp = 0.0;
         if (nes) {
             amp = az[i];
-            const double Tz = tz[i];
             if (lane < NC) L.bc[lane] = real ? psi_c : 0.0;
-            if (lane < NT) L.dd[lane] = (lane + 1 < N) ? exp(-A.cs->de[lane] / Tz) : 0.0;
+            if (lane < NT) L.dd[lane] = ws[(size_t)i * (NC + 1) * MT + lane];
         }
         wave_sync();
 
@@ -418,10 +431,14 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
     }
 
     // ---------------------------------------------------------------- backward sweep
+    // the row index recomputed here rather than kept live through the forward sweep
+    int lb;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lb));
+    const int kb = lb < MT ? lb : 0;
     double cr[NC], crn[NC];
     double yv = 0.0, yn = 0.0;
     {
-        const double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + kr;
+        const double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + kb;
 #pragma unroll
         for (int m = 0; m < NC; ++m) cr[m] = is_row ? wz[(size_t)m * MT] : 0.0;
         yv = is_row ? wz[(size_t)NC * MT] : 0.0;
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_ye_factor(YeFactorArgs A) {
     double dnext = 0.0;
     for (int i = I - 1; i >= 0; --i) {
         if (i > 0) {
-            const double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + kr;
+            const double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + kb;
 #pragma unroll
             for (int m = 0; m < NC; ++m) crn[m] = is_row ? wz[(size_t)m * MT] : 0.0;
             yn = is_row ? wz[(size_t)NC * MT] : 0.0;
@@ -596,7 +613,7 @@ hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
     TM_YE_DISPATCH(padded_groups(a.sh.N),
                    constexpr int WPB = ye_waves_per_block<NT>();
                    const long long blocks = (a.nray + WPB - 1) / WPB;
-                   hipLaunchKernelGGL(k_ye_factor<NT>, dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a))
+                   hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>()>), dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a))
     return hipGetLastError();
 }
 

@@ -158,6 +158,14 @@ struct alignas(16) YeLds {
 template <int NT>
 constexpr int ye_waves_per_block() { return NT <= 20 ? 4 : 2; }
 
+// value of v in lane p (p uniform over the wavefront), as a scalar
+__device__ __forceinline__ double lane_value(double v, int p) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, p);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), p);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // waves per SIMD the register allocation is held to: two up to 20 groups (256 VGPRs, no scratch), one above
 template <int NT>
 constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
@@ -370,29 +378,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             km = max((uint32_t)__builtin_amdgcn_readlane((int)km, 0), (uint32_t)__builtin_amdgcn_readlane((int)km, 32));
             const int p = 63 - (int)(km & 63u);
             const bool isp = lz == p;
-            if (isp) {
-#pragma unroll
-                for (int j = 0; j < MT; ++j) L.prow[j] = a[j];
-                L.prow[MT] = g;
-                L.prow[MT + 1] = bcoef;
-                L.plane[cc] = lane;
-            }
-            wave_sync();
-            // the whole pivot row is read before it is used, so its LDS reads are issued back to back and
-            // waited for once (one LDS latency per step instead of one per few columns)
-            double pr[MT + 2];
-#pragma unroll
-            for (int j = 0; j < MT + 2; ++j) pr[j] = L.prow[j];
-#pragma unroll
-            for (int j = 0; j < MT + 2; ++j) asm volatile("" : "+v"(pr[j]));
-            const double piv = pr[cc];
+            if (isp) L.plane[cc] = lane;
+            // the pivot row reaches every lane through scalar registers: each value is read from the pivot
+            // lane and used at once as the scalar operand of the row updates
+            const double piv = lane_value(ac, p);
             const double pinv = drcp(piv);
             const double fm = isp ? 0.0 : ac * pinv;
 #pragma unroll
             for (int j = 0; j < MT; ++j)
-                if (j != cc) a[j] = fma(-fm, pr[j], a[j]);
-            g = fma(-fm, pr[MT], g);
-            const double bpiv = pr[MT + 1];
+                if (j != cc) a[j] = fma(-fm, lane_value(a[j], p), a[j]);
+            g = fma(-fm, lane_value(g, p), g);
+            const double bpiv = lane_value(bcoef, p);
             a[cc] = isp ? bpiv : -fm * bpiv;
             // kept current in every step: left alone, the compiler defers these selects to the end of the
             // zone and holds every step's pivot and lane mask until then
@@ -400,8 +396,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             mypiv = isp ? piv : mypiv;
             mycol = isp ? cc : mycol;
             asm volatile("" : "+v"(used), "+v"(mypiv), "+v"(mycol));
-            wave_sync();
         }
+        wave_sync();                                   // plane[] is read by other lanes below
         // every pivot is some row's own pivot: a zero one is seen here, once per zone
         zp |= is_row && !(mypiv != 0.0);
 

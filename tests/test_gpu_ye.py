@@ -155,6 +155,41 @@ def test_full_size_rays_match_oracle():
     assert e < BAR and ey < BAR
 
 
+def test_bench_launch_all_16384_rays_sampled_rays_match_oracle():
+    """The coupled step as the benchmark times it: species 0 and 1 of all 16384 rays (540 zones x 20
+    groups, blocks of 41 rows) in one call with workspace for every ray, FP64, rtol 1e-12.  Four sampled
+    rays against the oracle, on the inputs of those rays copied from the device workload."""
+    say("case ye bench launch 16384 rays")
+    w = synth.make(4, device="cuda")
+    y = synth.ye_inputs(w, 4)
+    ctx = tm.Context(tm.problem_of(w, tm.PREC_FP64))
+    ctx.set_workspace(ctx.ye_workspace_bytes(0))
+    f = tm.DeviceFields.of(w)
+    psi = w.psi_n.clone()
+    ye = y.ye_n.clone()
+    st, stats = ctx.ye_newton_step(f, y, w.psi_n, psi, ye, 30, 1e-12, raise_on_status=False)
+    torch.cuda.synchronize()
+    assert st == tm.TM_OK
+    rays = [0, 5077, 12345, w.R - 1]
+    ri = torch.as_tensor(rays, device="cuda")
+    cell = lambda t: t[:, ri].cpu()
+    ws = dataclasses.replace(w, R=len(rays), r_edge=w.r_edge[ri].cpu(), e_edge=w.e_edge.cpu(), temp=w.temp[ri].cpu(),
+                             kappa_a=cell(w.kappa_a), eta=cell(w.eta), kappa_s=cell(w.kappa_s), psi_n=cell(w.psi_n),
+                             nes_amp=cell(w.nes_amp), nes_g=w.nes_g.cpu())
+    ys = synth.YeInputs(rho=y.rho[ri].cpu(), ye_n=y.ye_n[ri].cpu(), dka_dye=cell(y.dka_dye),
+                        deta_dye=cell(y.deta_dye), de_dT=y.de_dT[ri].cpu(), de_dye=y.de_dye[ri].cpu())
+    got_psi, got_ye = psi[:, ri].cpu().numpy(), ye[ri].cpu().numpy()
+    iters = stats["iters"][ri].cpu().numpy()
+    ctx.close()
+    del psi, ye, y, w, f, stats
+    torch.cuda.empty_cache()
+    ora = _oracle(ws, ys, 30, 1e-12)
+    e, ey = _compare(ws, got_psi, got_ye, ora)
+    say("  psi err", e, "ye err", ey, "iters", iters.tolist(), [res.iters for _, _, res in ora])
+    assert e < BAR and ey < BAR
+    assert iters.tolist() == [res.iters for _, _, res in ora]
+
+
 def test_lepton_number_is_conserved_on_the_gpu():
     """Zero-flux outer boundary: the converged coupled step keeps electrons + (nu_e - anti-nu_e)."""
     say("case ye lepton conservation")

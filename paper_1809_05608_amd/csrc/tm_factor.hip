@@ -96,7 +96,8 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     for (int j = threadIdx.x; j < NT * NT; j += kBlock) s_P[(j / NT) * PS + (j % NT)] = (T)A.cs->P[j / NT][j % NT];
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);     // uniform over the wave
     const bool in_group = lane < SPW * SL;                                   // lanes past the last group idle
     const int sub = in_group ? lane / SL : SPW - 1;
     const int k = in_group ? lane % SL : SL;                                 // idle lanes own no row
@@ -104,6 +105,12 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     const bool in_batch = sb < A.nsys;
     const long long sbc = in_batch ? sb : A.nsys - 1;                        // clamped for loads
     const long long sys = A.sys0 + sbc;                                      // global system index
+    // the same for lane ln, recomputed inside and after the zone loop rather than held live through it
+    auto system_of = [&](int ln) -> long long {
+        const int s_sub = ln < SPW * SL ? ln / SL : SPW - 1;
+        const long long s_b = (long long)blockIdx.x * SPB + wave * SPW + s_sub;
+        return A.sys0 + (s_b < A.nsys ? s_b : A.nsys - 1);
+    };
     const bool live = in_group && in_batch && (A.active == nullptr || A.active[sys] != 0);
     if (__ballot(live) == 0) return;                                         // whole wave idle
 
@@ -124,7 +131,6 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     const double* ks = A.f.kappa_s + cell0;
     const double* rhs = A.rhs + cell0;
     const double* tz = A.f.temp + (size_t)ray * I;
-    const double* az = (sh.terms & kNes) ? A.f.nes_amp + (size_t)sys * I : nullptr;
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
     // Workspace, interleaved by wave group: the SPW systems of group g keep, per zone i and column m,
@@ -132,7 +138,9 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     // load of column m is then one contiguous run (3 * 20 floats at N = 20) rather than SPW separate
     // pieces.  A last partial group has empty slots, which the workspace size allows for
     // (kWsPadSystems); lanes of a clamped system use that system's slot.
-    const long long wg = sbc / SPW;
+    // sbc / SPW, the same for every lane of the wave (a clamped lane's system is the batch's last, which lies
+    // in this wave whenever any lane of it is live), so the workspace bases stay scalar
+    const long long wg = (long long)blockIdx.x * (SPB / SPW) + wave;
     const int lo = (int)(sbc - wg * SPW) * NT + k;             // this lane's place in a run
     constexpr int zs = SPW * NT;                                // values per (zone, column) run
     T* wsC = reinterpret_cast<T*>(A.wsC) + (size_t)wg * SPW * I * NT * NT;
@@ -157,19 +165,33 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     // the guard compares magnitudes to about 2^-20 relative, ample for a growth threshold
     uint32_t gkey = 0;
     const RhsScale rsc = rhs_scale<T>(A, sys);
+    // FP64: NES neighbour factors exp(-(eps_{k+1} - eps_k)/T) of every zone, computed before the sweep and
+    // parked in the lane's own y slot of the zone, which the same lane overwrites only at the end of that zone
+    if constexpr (sizeof(T) == 8) {
+        if (nes && live && is_row) {
+            for (int i = 0; i < I; ++i)
+                wsY[(size_t)i * zs + lo] = (k + 1 < N) ? texp((T)(-de_k / tz[i])) : (T)0;
+        }
+    }
 
     for (int i = 0; i < I; ++i) {
         // lane index re-materialised per zone: comparisons with it are evaluated where used
         // instead of being hoisted out of the zone loop as dozens of live lane masks
         int kz = k;
         asm volatile("" : "+v"(kz));
+        // the system's cell offset likewise, so the per-array addresses are formed where used rather than
+        // held through the zone as one 64-bit pointer per array
+        int lnz;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lnz));
+        const long long sysz = system_of(lnz);
+        const size_t co = (size_t)sysz * I * N;
         // next zone, own group
         double psi_n1 = 0.0, sig_n1 = 0.0, lam_n1 = 1.0;
         if (i + 1 < I && real) {
             const size_t cn = (size_t)(i + 1) * N + kk;
-            psi_n1 = psi[cn];
-            sig_n1 = ka[cn] + et[cn];
-            lam_n1 = rcp_nr(sig_n1 + ks[cn]);
+            psi_n1 = A.psi[co + cn];
+            sig_n1 = A.f.kappa_a[co + cn] + A.f.eta[co + cn];
+            lam_n1 = rcp_nr(sig_n1 + A.f.kappa_s[co + cn]);
         }
         const double rlo = re[i], rhi = re[i + 1];
         const double V = shell_volume(rlo, rhi);
@@ -221,7 +243,7 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
             for (int kp = 0; kp < NT; ++kp) acc[kp] = -s0 * a[kp];
         }
         if (nes) {
-            const double amp = az[i];
+            const double amp = A.f.nes_amp[(size_t)sysz * I + i];
             const double Tz = tz[i];
             const T pk = (T)psi_c;
             const T ca = (T)(-c * amp);
@@ -253,7 +275,7 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
             } else {
                 if (is_row) {
                     L.bc[k] = real ? (T)psi_c : (T)0;
-                    L.dd[k] = (k + 1 < N) ? texp((T)(-de_k / Tz)) : (T)0;
+                    L.dd[k] = live ? wsY[(size_t)i * zs + lo] : (T)0;
                 }
                 wave_sync();
                 const T cap = ca * pk, cam = ca * ((T)1 - pk);
@@ -294,7 +316,7 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
         if (!real) bm = bp = bm_next = 0.0;
 
         // ---- right-hand side (and, for the transpose, the transposed block plus its Schur update)
-        T g = real ? (T)(rsc.in * rhs[(size_t)i * N + kk]) : (T)0;
+        T g = real ? (T)(rsc.in * A.rhs[co + (size_t)i * N + kk]) : (T)0;
         T bcoef;
         if constexpr (!TRANS) {
             g = fma(-(T)bm, ycar, g);
@@ -422,6 +444,10 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
 
     // zero-pivot report and, for diagonal pivots, the growth guard (any lane of the system)
     const bool lane_bad = is_row && (zp || gkey > abs_key_bits((T)A.growth_limit));
+    int lnb;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lnb));
+    const long long sysb = system_of(lnb);
+    const size_t cellb = (size_t)sysb * I * N;
     uint32_t any_bad;
     if constexpr (PIVOT) {
         any_bad = group_max<SL>(lane_bad ? 1u : 0u);
@@ -432,20 +458,20 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     }
     bool skip = false;
     if constexpr (PIVOT) {
-        if (live && k == 0 && any_bad && A.flags) A.flags[sys] |= 4;
+        if (live && k == 0 && any_bad && A.flags) A.flags[sysb] |= 4;
     } else {
         skip = any_bad != 0;                          // leave this system to the pivoting re-run
         if (live && k == 0 && any_bad) {
-            if (A.guard) A.guard[sys] = 1;
-            if (A.flags) A.flags[sys] |= 8;
+            if (A.guard) A.guard[sysb] = 1;
+            if (A.flags) A.flags[sysb] |= 8;
         }
     }
     const bool store_out = store && !skip;
 
     // ---------------------------------------------------------------- backward sweep
-    double* outp = A.psi_out ? A.psi_out + cell0 : nullptr;
-    double* xp = A.x ? A.x + cell0 : nullptr;
-    double* dxp = A.dx ? A.dx + cell0 : nullptr;
+    double* outp = A.psi_out ? A.psi_out + cellb : nullptr;
+    double* xp = A.x ? A.x + cellb : nullptr;
+    double* dxp = A.dx ? A.dx + cellb : nullptr;
     T cr[NT], crn[NT];
     T yv = (T)0, yn = (T)0;
     {
@@ -486,9 +512,9 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
         yv = yn;
     }
     if (live && !skip && k == 0 && A.psi_out) {
-        if (A.iters) A.iters[sys] += 1;
-        if (A.pending) A.pending[sys] = 1;               // trial psi + delta awaits the line search
-        if (A.alpha) A.alpha[sys] = 1.0;
+        if (A.iters) A.iters[sysb] += 1;
+        if (A.pending) A.pending[sysb] = 1;               // trial psi + delta awaits the line search
+        if (A.alpha) A.alpha[sysb] = 1.0;
     }
 }
 
@@ -499,16 +525,21 @@ size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
     return (size_t)I * NT * (NT + 1) * es;
 }
 
+// waves per SIMD the register allocation is held to: two for the FP64 forward kernel with diagonal pivots up to
+// 20 groups (it fits 256 VGPRs without scratch and runs a third faster than at one), one otherwise
 template <typename T, int NT, bool TRANS, bool PIVOT>
-__global__ __launch_bounds__(kBlock) void k_factor(FactorArgs A) {
+constexpr int factor_waves_per_eu() { return (sizeof(T) == 8 && NT <= 20 && !TRANS && !PIVOT) ? 2 : 1; }
+
+template <typename T, int NT, bool TRANS, bool PIVOT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(factor_waves_per_eu<T, NT, TRANS, PIVOT>()))) void k_factor(FactorArgs A) {
     factor_sweeps<T, NT, TRANS, PIVOT>(A);
 }
 
-// The float32 forward kernel with diagonal pivots (the mixed-precision Newton update) held to 128 VGPRs,
-// four waves per SIMD: it fits without spilling, and left alone the compiler settles a few registers
-// above the limit and runs three.
+// The float32 forward kernel with diagonal pivots (the mixed-precision Newton update) held to five waves per
+// SIMD (102 VGPRs; its LDS allows five blocks per CU), four with the lapse terms, which spill at five: both fit
+// without scratch, and left alone the compiler settles a few registers above 128 and runs three.
 template <int NT, bool LAPSE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_factor_f32(FactorArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LAPSE ? 4 : 5))) void k_factor_f32(FactorArgs A) {
     factor_sweeps<float, NT, false, false, LAPSE>(A);
 }
 

@@ -18,9 +18,9 @@ BUILD = os.path.join(ROOT, "_build")
 LLVM = "/opt/rocm/llvm/bin"
 SOURCES = ["tm_residual", "tm_factor", "tm_ye", "tm_energy"]
 
-# kernels that may use scratch: the debug Jacobian output, the 32-group FP64 factor variants, and the
-# per-zone temperature update, none of them on a timed path
-ALLOWED = [r"k_blocks", r"k_factorIdLi32E", r"k_ye_temperature"]
+# kernels that may use scratch: the debug Jacobian output and the per-zone temperature update, neither
+# on a timed path
+ALLOWED = [r"k_blocks", r"k_ye_temperature"]
 
 
 def _kernel_scratch(obj, tmp):

@@ -16,7 +16,8 @@
 //   k_ye_factor       one wavefront per ray: lane r owns row r of the coupled block.  Per zone the row is
 //                     assembled in registers, the Schur complement with the previous factor row is
 //                     formed, and in-place Gauss-Jordan elimination with partial pivoting (pivot search
-//                     as a max over the wavefront, pivot row broadcast through LDS) produces
+//                     as a max over the wavefront, pivot row read from the pivot lane into scalar
+//                     registers) produces
 //                     C_i = Ahat_i^{-1} diag(bp_i) and y_i; the backward sweep x_i = y_i - C_i x_{i+1}
 //                     applies the Newton update.
 //   k_ye_backtrack    line-search move-back of rejected trials.

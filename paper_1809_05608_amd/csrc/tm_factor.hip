@@ -237,10 +237,13 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
         //      diagonal: 1 + transport + c dt (eta + kappa_a) + c dt sum_k' [K^in psi + K^out (1 - psi)]
         T row[NT];                                     // assembled row (only kept for the transpose)
         T* acc = TRANS ? row : a;
-        {
-            const T s0 = TRANS ? (T)0 : (real ? (T)bm : (T)0);
+        if constexpr (TRANS) {
 #pragma unroll
-            for (int kp = 0; kp < NT; ++kp) acc[kp] = -s0 * a[kp];
+            for (int kp = 0; kp < NT; ++kp) row[kp] = (T)0;
+        } else {
+            const T s0 = real ? (T)bm : (T)0;
+#pragma unroll
+            for (int kp = 0; kp < NT; ++kp) a[kp] = -s0 * a[kp];
         }
         if (nes) {
             const double amp = A.f.nes_amp[(size_t)sysz * I + i];
@@ -327,9 +330,15 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
                 for (int kp = 0; kp < NT; ++kp) L.fix[k][kp] = row[kp];
             }
             wave_sync();
+            // the previous factor row, as this lane stored it at the end of the previous zone (read back
+            // rather than held in registers through the assembly)
             const T s = real ? (T)bp_prev : (T)0;
+            const T* qp = wsC + (size_t)(i > 0 ? i - 1 : 0) * NT * zs + lo;
 #pragma unroll
-            for (int m = 0; m < NT; ++m) a[m] = fma(-s, a[m], is_row ? L.fix[m][kr] : (T)0);
+            for (int m = 0; m < NT; ++m) {
+                const T prev = (i > 0 && store && m < N) ? qp[(size_t)m * zs] : (T)0;
+                a[m] = fma(-s, prev, is_row ? L.fix[m][kr] : (T)0);
+            }
             wave_sync();
             g = fma(-s, ycar, g);
             bcoef = (T)bm_next;
@@ -525,10 +534,11 @@ size_t factor_ws_bytes_per_system(int I, int N, bool fp32) {
     return (size_t)I * NT * (NT + 1) * es;
 }
 
-// waves per SIMD the register allocation is held to: two for the FP64 forward kernel with diagonal pivots up to
-// 20 groups (it fits 256 VGPRs without scratch and runs a third faster than at one), one otherwise
+// waves per SIMD the register allocation is held to: two for the FP64 kernels with diagonal pivots (forward and
+// transposed) up to 20 groups (they fit 256 VGPRs without scratch and run a third faster than at one), one
+// otherwise
 template <typename T, int NT, bool TRANS, bool PIVOT>
-constexpr int factor_waves_per_eu() { return (sizeof(T) == 8 && NT <= 20 && !TRANS && !PIVOT) ? 2 : 1; }
+constexpr int factor_waves_per_eu() { return (sizeof(T) == 8 && NT <= 20 && !PIVOT) ? 2 : 1; }
 
 template <typename T, int NT, bool TRANS, bool PIVOT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(factor_waves_per_eu<T, NT, TRANS, PIVOT>()))) void k_factor(FactorArgs A) {

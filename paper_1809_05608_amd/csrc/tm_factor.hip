@@ -546,7 +546,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(factor_w
 }
 
 // The float32 forward kernel with diagonal pivots (the mixed-precision Newton update) held to five waves per
-// SIMD (102 VGPRs; its LDS allows five blocks per CU), four with the lapse terms, which spill at five: both fit
+// SIMD (95 VGPRs; its LDS allows five blocks per CU), four with the lapse terms, which spill at five: both fit
 // without scratch, and left alone the compiler settles a few registers above 128 and runs three.
 template <int NT, bool LAPSE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LAPSE ? 4 : 5))) void k_factor_f32(FactorArgs A) {

@@ -67,6 +67,12 @@ FLAG_OVERFILL = 2        # the limiter moved neutrinos
 FLAG_OVERFILL_CLAMP = 4  # the limiter hit the psi_{k+2} >= 0 bound (approximate case)
 
 
+def _work_dtype(x) -> type:
+    """float64, or the wider floating type of x (np.longdouble), so that the same steps can be
+    repeated in extended precision to measure their own rounding."""
+    return np.result_type(np.asarray(x).dtype, np.float64)
+
+
 # ---------------------------------------------------------------- grid quantities (eqs. a01, a01b, p4)
 
 def centers(edges: np.ndarray) -> np.ndarray:
@@ -206,7 +212,7 @@ def overfill_limit(psi: np.ndarray, edges: np.ndarray):
     k+2 so that number (eq. a81a) and energy (eq. a81b) are unchanged (eqs. a81c, a81d).
 
     Returns (psi_new, flags)."""
-    psi = np.array(psi, dtype=np.float64, copy=True)
+    psi = np.array(psi, dtype=_work_dtype(psi), copy=True)
     eps = centers(edges)
     de = edges[..., 1:] - edges[..., :-1]
     flags = np.zeros(psi.shape[:-1], dtype=np.int32)
@@ -246,7 +252,8 @@ def lagrangian_displacement(e_edge, dlna, dlnR, dlnb, eddington, shape):
 
     dlna, dlnR, dlnb: arrays broadcasting to the leading shape (one value per zone)."""
     h = edge_eddington(eddington, shape)
-    dlna, dlnR, dlnb = (np.asarray(x, dtype=np.float64)[..., None] for x in (dlna, dlnR, dlnb))
+    dt = _work_dtype(e_edge)
+    dlna, dlnR, dlnb = (np.asarray(x, dtype=dt)[..., None] for x in (dlna, dlnR, dlnb))
     s = 1.0 + (dlna - dlnR) - (dlnb - dlnR) * h
     return s * e_edge
 
@@ -257,15 +264,16 @@ def energy_advect(psi, e_edge, rho_old=1.0, rho_new=1.0, a_old=1.0, a_new=1.0, d
 
     Zone quantities (rho, lapse a, dR/R, db/b) broadcast to the leading shape.  Returns
     (psi_new, xi, flags)."""
-    psi = np.asarray(psi, dtype=np.float64)
+    dt = _work_dtype(psi)
+    psi = np.asarray(psi, dtype=dt)
     shape = psi.shape
     tgt = np.broadcast_to(e_edge, shape[:-1] + (shape[-1] + 1,))
-    a_old, a_new = np.asarray(a_old, dtype=np.float64), np.asarray(a_new, dtype=np.float64)
+    a_old, a_new = np.asarray(a_old, dtype=dt), np.asarray(a_new, dtype=dt)
     dlna = a_new / a_old - 1.0
     src = lagrangian_displacement(e_edge, dlna, dlnR, dlnb, eddington, shape)
     # eq. a78: psi' (E^2 dE)' = (rho a^3)^{n+1} / (rho a^3)^n psi (E^2 dE), i.e. N' = r W psi
     r = (np.asarray(rho_new) * a_new ** 3) / (np.asarray(rho_old) * a_old ** 3)
-    N = np.asarray(r, dtype=np.float64)[..., None] * weights(tgt) * psi
+    N = np.asarray(r, dtype=dt)[..., None] * weights(tgt) * psi
     return _remap_and_limit(psi, N, src, tgt)
 
 
@@ -274,10 +282,11 @@ def lapse_remap(psi, e_edge, a_old, a_new):
 
     The local grid edges move from E/a^n to E/a^{n+1} (eq. p1); psi on the old grid holds
     N_k = psi_k W_k(E/a^n) neutrinos (eq. p2).  Returns (psi_new, xi, flags)."""
-    psi = np.asarray(psi, dtype=np.float64)
+    dt = _work_dtype(psi)
+    psi = np.asarray(psi, dtype=dt)
     shape = psi.shape
-    a_old = np.asarray(a_old, dtype=np.float64)[..., None]
-    a_new = np.asarray(a_new, dtype=np.float64)[..., None]
+    a_old = np.asarray(a_old, dtype=dt)[..., None]
+    a_new = np.asarray(a_new, dtype=dt)[..., None]
     src = np.broadcast_to(e_edge / a_old, shape[:-1] + (shape[-1] + 1,))
     tgt = np.broadcast_to(e_edge / a_new, shape[:-1] + (shape[-1] + 1,))
     N = weights(src) * psi

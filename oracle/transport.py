@@ -377,8 +377,8 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
 
     Starts from psi0 (default psi^n).  Each update solves J delta = -G (eq. a62ae) and is
     globalised by backtracking on r = max|G|: the trial psi + delta is accepted when
-    r_trial <= (1 - 1e-4 alpha) r, else alpha is halved (the trial moved back by
-    (alpha_new - alpha) delta) down to alpha = 2^-8, which is taken regardless.  Within 1000x
+    r_trial <= (1 - 1e-4 alpha) r, else alpha is halved (the trial becomes psi + alpha delta)
+    down to alpha = 2^-8, which is taken regardless.  Within 1000x
     of the target (the rounding level of G when rtol = 0) a full step is taken without the test.  The paper's scheme is plain
     Newton; without the line search the strongly spiked stress rays diverge (psi overshoots
     the Pauli limit 1 and the residual grows), with it they converge quadratically.
@@ -408,9 +408,8 @@ def newton(sys: System, psi_n: np.ndarray, psi0: Optional[np.ndarray] = None,
         rt = float(np.max(np.abs(Gt)))
         near = r <= 1e3 * target
         while not near and not rt <= (1.0 - ARMIJO_C * alpha) * r and alpha > ALPHA_MIN:
-            alpha_new = 0.5 * alpha
-            trial = trial + (alpha_new - alpha) * delta
-            alpha = alpha_new
+            alpha = 0.5 * alpha
+            trial = psi + alpha * delta
             Gt = residual(sys, psi_n, trial)
             rt = float(np.max(np.abs(Gt)))
         prev = r

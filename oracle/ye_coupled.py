@@ -231,9 +231,8 @@ def newton(cs: CoupledSystem, u_n: np.ndarray, u0: Optional[np.ndarray] = None,
         rt = float(np.max(np.abs(Gt)))
         near = r <= 1e3 * target
         while not near and not rt <= (1.0 - ARMIJO_C * alpha) * r and alpha > ALPHA_MIN:
-            alpha_new = 0.5 * alpha
-            trial = trial + (alpha_new - alpha) * delta
-            alpha = alpha_new
+            alpha = 0.5 * alpha
+            trial = u + alpha * delta
             Gt = residual(cs, u_n, trial)
             rt = float(np.max(np.abs(Gt)))
         prev = r

@@ -23,7 +23,9 @@ def zone_err(got, ref):
 
     psi_new = (N_k + xi D_k) / W_k combines a zone's numbers with O(1) weights, so its rounding is a few
     ulp of the zone's largest occupation; a group far down the spectrum whose inflow and outflow nearly
-    cancel has no better relative accuracy (the oracle in float64 and in long double differ there)."""
+    cancel has no better relative accuracy: the oracle in float64 and in long double differ by up to 5e-12
+    relative to such a group and by under 2e-14 relative to its zone
+    (test_oracle_energy.test_float64_rounding_of_the_update_is_zone_relative)."""
     got, ref = np.asarray(got), np.asarray(ref)
     scale = np.maximum(np.abs(ref).max(-1, keepdims=True), TAU)
     return float(np.max(np.abs(got - ref) / scale)) if ref.size else 0.0
@@ -110,8 +112,10 @@ def test_energy_advect_matches_oracle(shape, mode):
     assert np.array_equal(flags, rflags)
     assert e_psi <= PSI_BAR and e_xi <= XI_BAR
     # xi of eq. p8 is not bounded, so on very coarse grids (N = 2, 3) it can ask for more than a group
-    # holds and drive it negative; the sign pattern must then be the oracle's
-    assert np.array_equal(psi < 0.0, rpsi < 0.0) or e_psi <= PSI_BAR
+    # holds and drive it negative; the sign pattern must then be the oracle's wherever the value is
+    # resolved, i.e. above the bar relative to its zone's largest occupation
+    resolved = np.abs(rpsi) > PSI_BAR * np.abs(rpsi).max(-1, keepdims=True)
+    assert np.array_equal((psi < 0.0)[resolved], (rpsi < 0.0)[resolved])
 
 
 def test_overfill_limiter_matches_oracle():

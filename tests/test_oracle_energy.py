@@ -309,3 +309,142 @@ def test_displacement_beyond_a_group_is_flagged_and_left_unchanged():
                                       eddington=np.stack([np.full(n, 0.4), np.linspace(0.34, 1.0, n)]))
     assert flags[1] == ea.FLAG_DISPLACEMENT and np.array_equal(out[1], psi[1])
     assert flags[0] == 0
+
+
+# ---------------------------------------------------------------- eq. a79 against the angular physics
+
+def beam_average(beta, x_R, x_b):
+    """Eddington factor <mu^2> of an intensity I(mu) ~ exp(beta mu), and the intensity-weighted mean of
+    the first-order energy change of a beam at direction cosine mu in a fluid element stretched radially by
+    db/b = x_b and transversely by dR/R = x_R: the momentum component along each axis scales inversely
+    with the element's length along it, so d ln eps = -mu^2 x_b - (1 - mu^2) x_R.  Gauss-Legendre
+    quadrature over mu in [-1, 1]."""
+    mu, wq = np.polynomial.legendre.leggauss(64)
+    I = wq * np.exp(beta * mu)
+    eta2 = float(np.sum(I * mu * mu) / np.sum(I))
+    s = 1.0 + float(np.sum(I * (-mu * mu * x_b - (1.0 - mu * mu) * x_R)) / np.sum(I))
+    return eta2, s
+
+
+@pytest.mark.parametrize("beta", [0.0, 2.0, 8.0, 40.0])
+def test_eq_a79_energy_shift_is_the_beam_average(beta):
+    """Eq. a79 with dR/R != db/b and a constant Eddington factor: every group edge moves by the beam
+    average s above, so the mean energy of each zone changes by exactly s (the remap keeps number and
+    energy) and its number by the density ratio of eq. a78 (the element's volume changes by
+    (1 + dR/R)^2 (1 + db/b))."""
+    n = 20
+    e = np.geomspace(2.0, 300.0, n + 1)
+    x_R, x_b = -3e-3, 5e-3
+    eta2, s = beam_average(beta, x_R, x_b)
+    psi = random_state((16,), n, 21)
+    rho_ratio = 1.0 / ((1.0 + x_R) ** 2 * (1.0 + x_b))
+    out, xi, flags = ea.energy_advect(psi, e, rho_old=1.0, rho_new=rho_ratio, dlnR=x_R, dlnb=x_b,
+                                      eddington=np.full((16, n), eta2))
+    assert np.all(flags == 0)
+    n0, e0 = ea.number_and_energy(psi, e)
+    n1, e1 = ea.number_and_energy(out, e)
+    assert np.allclose(n1, rho_ratio * n0, rtol=1e-14, atol=0)
+    assert np.allclose((e1 / n1) / (e0 / n0), s, rtol=1e-13, atol=0)
+
+
+def test_eq_a79_pin_catches_a_sign_flip_of_the_eddington_term(monkeypatch):
+    """A planted sign error in the (db/b - dR/R) eta2 term of eq. a79 fails the beam-average pin."""
+    def flipped(e_edge, dlna, dlnR, dlnb, eddington, shape):
+        h = ea.edge_eddington(eddington, shape)
+        dlna, dlnR, dlnb = (np.asarray(x, dtype=np.float64)[..., None] for x in (dlna, dlnR, dlnb))
+        return (1.0 + (dlna - dlnR) + (dlnb - dlnR) * h) * e_edge
+    monkeypatch.setattr(ea, "lagrangian_displacement", flipped)
+    with pytest.raises(AssertionError):
+        test_eq_a79_energy_shift_is_the_beam_average(2.0)
+
+
+def test_eq_a79_per_group_eddington_factors():
+    """Groups 0-9 with one angular distribution and 10-19 with another: the edges inside each set move by
+    that set's beam average, the edge between them by the mean of the two (its Eddington factor is the
+    mean of its groups' and eq. a79 is linear in it), and the end edges by their group's.  The energy
+    after the step is the number of each displaced group (eq. a78) at its displaced centre (eq. a01),
+    which the remap keeps."""
+    n = 20
+    e = np.geomspace(2.0, 300.0, n + 1)
+    x_R, x_b = 4e-3, -6e-3
+    (h_lo, s_lo), (h_hi, s_hi) = beam_average(0.5, x_R, x_b), beam_average(12.0, x_R, x_b)
+    edd = np.where(np.arange(n) < 10, h_lo, h_hi)[None, :].repeat(8, 0)
+    psi = random_state((8,), n, 22)
+    rho_ratio = 1.0 / ((1.0 + x_R) ** 2 * (1.0 + x_b))
+    out, xi, flags = ea.energy_advect(psi, e, rho_new=rho_ratio, dlnR=x_R, dlnb=x_b, eddington=edd)
+    assert np.all(flags == 0)
+    s_edge = np.where(np.arange(n + 1) < 10, s_lo, s_hi)
+    s_edge[10] = 0.5 * (s_lo + s_hi)
+    moved = e * s_edge
+    N_moved = rho_ratio * ea.weights(e) * psi
+    e_expected = np.sum(N_moved * ea.centers(moved), axis=-1)
+    n1, e1 = ea.number_and_energy(out, e)
+    assert np.allclose(n1, N_moved.sum(-1), rtol=1e-14, atol=0)
+    assert np.allclose(e1, e_expected, rtol=1e-13, atol=0)
+
+
+def test_lagrangian_lapse_change_equals_homologous_compression():
+    """In eq. a79 the lapse enters as da/a - dR/R and in eq. a78 through rho a^3: a lapse change
+    a^{n+1}/a^n = 1 + x at fixed rho, R and b is the same update as a homologous compression
+    dR/R = db/b = -x with rho^{n+1}/rho^n = (1 + x)^3 at a fixed lapse, whatever the Eddington factors
+    (the eta2 term vanishes for both), and shifts the mean energy by exactly 1 + x."""
+    n = 20
+    e = np.geomspace(2.0, 300.0, n + 1)
+    psi = random_state((12,), n, 23)
+    edd = np.clip(np.random.default_rng(24).uniform(1 / 3, 1.0, (12, n)), 1 / 3, 1.0)
+    x = 7e-3
+    a0 = np.random.default_rng(25).uniform(0.7, 0.95, 12)
+    lap, _, fl_a = ea.energy_advect(psi, e, a_old=a0, a_new=a0 * (1.0 + x), eddington=edd)
+    hom, _, fl_h = ea.energy_advect(psi, e, rho_new=(1.0 + x) ** 3, dlnR=-x, dlnb=-x, eddington=edd)
+    assert np.all(fl_a == 0) and np.all(fl_h == 0)
+    assert np.allclose(lap, hom, rtol=1e-13, atol=1e-15)
+    n0, e0 = ea.number_and_energy(psi, e)
+    n1, e1 = ea.number_and_energy(lap, e)
+    assert np.allclose(n1, (1.0 + x) ** 3 * n0, rtol=1e-14, atol=0)
+    assert np.allclose((e1 / n1) / (e0 / n0), 1.0 + x, rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- float64 rounding of the update
+
+def gpu_test_inputs(S, R, I, N, seed, scale=1.0, psi_hi=0.9):
+    """The recipe of the device parity test: Fermi-Dirac spectra, percent-level rho/lapse/radius changes,
+    group- and zone-dependent Eddington factors."""
+    r = np.random.default_rng(seed)
+    e_edge = 2.0 * 150.0 ** (np.arange(N + 1) / N)
+    eps = ea.centers(e_edge)
+    T = r.uniform(3.0, 12.0, (S, R, I, 1))
+    psi = psi_hi / (np.exp((eps - 2.0 * T) / T) + 1.0)
+    rho_old = r.uniform(1e8, 1e12, (R, I))
+    rho_new = rho_old * (1.0 + 0.01 * scale * r.standard_normal((R, I)))
+    a_old = r.uniform(0.8, 0.99, (R, I))
+    a_new = a_old * (1.0 + 0.005 * scale * r.standard_normal((R, I)))
+    dlnR = 0.01 * scale * r.standard_normal((R, I))
+    dlnb = 0.01 * scale * r.standard_normal((R, I))
+    edd = np.clip(1.0 / 3.0 + 0.3 * r.uniform(0, 1, (S, R, I, 1)) * np.linspace(0, 1, N), 1 / 3, 1)
+    return dict(e_edge=e_edge, psi=psi, rho_old=rho_old, rho_new=rho_new, a_old=a_old, a_new=a_new,
+                dlnR=dlnR, dlnb=dlnb, edd=edd)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 40, 20), (1, 4, 30, 13), (1, 2, 50, 8)])
+def test_float64_rounding_of_the_update_is_zone_relative(shape):
+    """The update of the oracle in float64 against the same steps in long double (np.longdouble, 64-bit
+    mantissa): the difference of each group is a few ulp of its zone's largest occupation (below 1e-13 of
+    it), while relative to the group itself it reaches far more in tail groups whose inflow and outflow
+    nearly cancel.  This is why the device parity bar for psi is zone-relative (1e-12), and xi's relative
+    rounding of about 2^-53 / |s - 1| is why its bar is 1e-8."""
+    d = gpu_test_inputs(*shape, seed=sum(shape))
+    ld = {k: np.asarray(v, dtype=np.longdouble) for k, v in d.items()}
+    kw = lambda z: dict(rho_old=z["rho_old"], rho_new=z["rho_new"], a_old=z["a_old"], a_new=z["a_new"],  # noqa: E731
+                        dlnR=z["dlnR"], dlnb=z["dlnb"], eddington=z["edd"])
+    p64, xi64, f64 = ea.energy_advect(d["psi"], d["e_edge"], **kw(d))
+    pld, xild, fld = ea.energy_advect(ld["psi"], ld["e_edge"], **kw(ld))
+    assert pld.dtype == np.longdouble
+    assert np.array_equal(f64, fld)
+    pld = pld.astype(np.float64)
+    scale = np.maximum(np.abs(pld).max(-1, keepdims=True), 1e-30)
+    zone = float(np.max(np.abs(p64 - pld) / scale))
+    own = float(np.max(np.abs(p64 - pld) / np.maximum(np.abs(pld), 1e-30)))
+    xrel = float(np.max(np.abs(xi64 - xild.astype(np.float64)) / np.abs(xild.astype(np.float64))))
+    assert zone < 1e-13
+    assert own > 10.0 * zone          # relative to the group itself the rounding is far larger
+    assert xrel < 1e-9

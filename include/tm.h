@@ -42,9 +42,10 @@
  *      sys   [S][R]         every tm_stats array
  *      e_edge [N+1] (MeV) and nes_g [N][N] are shared by all systems.
  *  - One context is bound to one HIP stream given at creation; work is ordered on
- *    that stream.  A context is not thread-safe.  tm_newton_step synchronises the
- *    stream (it reads back a per-iteration count of unconverged systems); the other
- *    entry points are asynchronous.
+ *    that stream.  A context is not thread-safe.  tm_newton_step, tm_ye_newton_step,
+ *    tm_factor_solve and tm_adjoint_step synchronise the stream (they read back counts of
+ *    unconverged systems, of systems for the pivoting re-run, or of zero pivots); the
+ *    other entry points are asynchronous.
  *  - Errors are returned, never thrown.  Invalid shapes or null required pointers
  *    return TM_ERR_INVALID_ARG before any device work; HIP failures return
  *    TM_ERR_HIP with the message available from tm_last_error.
@@ -185,7 +186,9 @@ tm_status tm_assemble(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
  * the guard (default 16).  rhs and x are cell arrays and may alias.  In TM_PREC_MIXED the
  * factorisation and solve run in float32 on the right-hand side divided by a power of two
  * near its largest magnitude in the system (so residuals below the float32 range still
- * solve); x is the float32 solution widened and scaled back.                         */
+ * solve); x is the float32 solution widened and scaled back.  Returns TM_ERR_SINGULAR when
+ * some system meets an exactly zero pivot even with partial pivoting (its block is singular;
+ * its x then holds non-finite values, the other systems are solved).                   */
 tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
                           const double *rhs, double *x, int32_t transpose);
 
@@ -208,7 +211,9 @@ tm_status tm_newton_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
  * and returns the vector-Jacobian products of the objective through the solution:
  *   g_theta = -mu^T dG/dtheta  for theta in {kappa_a, eta, kappa_s, nes_amp},
  *   mu itself is dJ/dpsi^n (dG/dpsi^n = -1).
- * Every gradient pointer may be NULL to skip it; mu must not be NULL.  Always FP64. */
+ * Every gradient pointer may be NULL to skip it; mu must not be NULL.  Always FP64.
+ * Returns TM_ERR_SINGULAR as tm_factor_solve does (mu and the gradients of such a system
+ * are then non-finite).                                                            */
 tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
                           const double *psi_np1, const double *seed, double *mu,
                           double *g_kappa_a, double *g_eta, double *g_kappa_s,

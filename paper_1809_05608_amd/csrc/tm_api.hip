@@ -363,12 +363,30 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     return TM_OK;
 }
 
+// TM_ERR_SINGULAR when some system of the last factorisation met an exactly zero pivot (with partial
+// pivoting, so the block is singular): its solution holds non-finite values.  Synchronises the stream.
+tm_status check_zero_pivots(tm_ctx* c) {
+    TM_TRY(hip_check(c, tmk::launch_count_bits(c->flags, n_systems(c->p), TM_FLAG_ZERO_PIVOT, c->count, c->stream),
+                     "count kernel"));
+    TM_TRY(hip_check(c, hipMemcpyAsync(c->h_count, c->count, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                     "copy count"));
+    TM_TRY(hip_check(c, hipStreamSynchronize(c->stream), "stream sync"));
+    if (*c->h_count > 0)
+        return set_err(c, TM_ERR_SINGULAR, std::to_string(*c->h_count) + " system(s) with an exactly zero pivot");
+    c->err.clear();
+    return TM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* tm_status_string(tm_status s) {
-    switch (s) {
+    // a C caller may pass any int: read the argument's bytes rather than load it as the enumeration
+    // (a value outside the enumeration's range is undefined behaviour in C++)
+    int v;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case TM_OK: return "TM_OK";
         case TM_ERR_INVALID_ARG: return "TM_ERR_INVALID_ARG";
         case TM_ERR_HIP: return "TM_ERR_HIP";
@@ -509,7 +527,9 @@ tm_status tm_factor_solve(tm_ctx* c, const tm_inputs* in, const double* psi, con
     if (fp32)   // per-system max |rhs| for the power-of-two scaling of the float32 solve
         TM_TRY(hip_check(c, tmk::launch_sys_absmax(rhs, n_systems(c->p), (long long)c->p.n_zones * c->p.n_groups,
                                                    c->res, c->stream), "rhs scale kernel"));
-    return run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, fp32, transpose != 0, nullptr, fp32 ? c->res : nullptr);
+    TM_TRY(run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, fp32, transpose != 0, nullptr,
+                      fp32 ? c->res : nullptr));
+    return check_zero_pivots(c);
 }
 
 tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, double* psi, int32_t max_iter,
@@ -628,7 +648,7 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
         TM_TRY(hip_check(c, tmk::launch_vjp(sh, fields_of(*in), c->consts, psi_np1, mu, g_ka, g_eta, g_ks, g_amp,
                                             c->stream),
                          "vjp kernel"));
-    return TM_OK;
+    return check_zero_pivots(c);
 }
 
 size_t tm_ye_workspace_bytes(const tm_problem* p, int64_t batch_rays) {

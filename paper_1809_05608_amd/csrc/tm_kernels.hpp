@@ -92,6 +92,9 @@ hipError_t launch_count_active(const int* active, long long n, int* count, hipSt
 hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int* backtrack, double* alpha,
                             hipStream_t st);
 
+// *count = number of entries j with (flags[j] & mask) != 0
+hipError_t launch_count_bits(const int* flags, long long n, int mask, int* count, hipStream_t st);
+
 // active_out[j] = 1 where guard[j] != 0 (else 0); *count = number of such systems
 hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st);
 

@@ -1,9 +1,10 @@
-// FP64 zone-parallel kernels of libtm: grid constants, residual with per-system norms
-// and conservation sums, debug Jacobian blocks, and the adjoint vector-Jacobian product.
+// FP64 kernels of libtm over cells: grid constants, residual with per-system norms and
+// conservation sums, debug Jacobian blocks, and the adjoint vector-Jacobian product.
 //
-// Mapping: one 256-thread block per (species, ray) system; each thread owns whole
-// radial zones (strided), computes all N groups of a zone in registers, and the block
-// reduces per-system quantities in a fixed order (deterministic, no atomics).
+// Mapping of the residual and VJP kernels: one 256-thread block per (species, ray) system,
+// one thread per cell (zone, group) of a chunk of zones; each edge flux is computed once
+// and shared through LDS, and the block reduces per-system quantities in a fixed order
+// (deterministic, no atomics).
 #include <algorithm>
 
 #include "tm_kernels.hpp"
@@ -744,6 +745,20 @@ __global__ __launch_bounds__(kBlock) void k_mark(const int* __restrict__ guard, 
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) *count = (int)s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_bits(const int* __restrict__ flags, long long n, int mask,
+                                                       int* count) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (long long j = threadIdx.x; j < n; j += kBlock) s += (flags[j] & mask) != 0;
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *count = (int)s;
+}
+
+hipError_t launch_count_bits(const int* flags, long long n, int mask, int* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_bits, dim3(1), dim3(kBlock), 0, st, flags, n, mask, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_mark(const int* guard, long long n, int* active_out, int* count, hipStream_t st) {

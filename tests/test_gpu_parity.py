@@ -275,6 +275,35 @@ def test_iteration_cap_is_reported():
     assert np.all(stats["flags"] & tm.FLAG_NOT_CONVERGED) and np.all(stats["iters"] == 1)
 
 
+@pytest.mark.parametrize("precision", [tm.PREC_FP64, tm.PREC_MIXED])
+def test_singular_block_is_reported(precision):
+    """A block with an exactly zero column, made from host inputs: emission/absorption only, c dt = 1,
+    kappa_a = -1 and eta = 0 in one cell, so that diagonal entry 1 + c dt (kappa_a + eta) is exactly 0 in
+    both precisions and no row below it can serve as a pivot.  The solve and the adjoint return
+    TM_ERR_SINGULAR (after the partial-pivoting re-run); the other system's solution stays exact."""
+    say("case singular block", precision)
+    w = synth.make_custom(S=1, R=2, I=3, N=4, c_dt=1.0, terms=tm.TERM_EMABS, outer_bc=0)
+    ka = torch.full_like(w.kappa_a, 0.25)
+    et = torch.zeros_like(w.eta)
+    ka[0, 1, 2, 3] = -1.0
+    w = dataclasses.replace(w, kappa_a=ka, eta=et, kappa_s=torch.full_like(w.kappa_s, 2.0))
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd, precision)
+    rhs = torch.ones_like(wd.psi_n)
+    x = torch.empty_like(rhs)
+    with pytest.raises(tm.TMError) as e:
+        ctx.factor_solve(f, wd.psi_n, rhs, x, False)
+    assert e.value.status == 3                      # TM_ERR_SINGULAR
+    xs = x.cpu().numpy()
+    np.testing.assert_allclose(xs[0, 0], 1.0 / 1.25, rtol=1e-7)   # diagonal blocks 1 + c dt kappa_a
+    assert not np.all(np.isfinite(xs[0, 1]))
+    if precision == tm.PREC_FP64:
+        mu = torch.empty_like(rhs)
+        with pytest.raises(tm.TMError) as e:
+            ctx.adjoint_step(f, wd.psi_n, wd.psi_n, rhs, mu)
+        assert e.value.status == 3
+
+
 def test_binding_rejects_bad_tensors():
     say("case binding checks")
     w = synth.make_custom(S=1, R=2, I=8, N=6).to("cuda")

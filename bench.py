@@ -30,28 +30,69 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ray·zone·group Newton updates/s, mixed vs FP64 at ≤1e-8 rel err; % roofline"
 TAU = 1e-30
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz without packed-FP32 math
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.6, FP64 and non-packed FP32 VALU
+# MI355X published peaks: FP64 vector/matrix 78.6 TFLOP/s; FP32 157.3 TFLOP/s (matrix cores, or packed
+# FP32 on the vector units); HBM3E 8 TB/s
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+KERNEL_F32 = "k_factor_f32<20>"
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def factor_flops_per_cell(N: int) -> float:
-    """Algorithmic flops per cell per Newton iteration: 2N^2 + 20N (block inverse dominant)."""
+def iteration_flops_per_cell(N: int) -> float:
+    """Algorithmic flops per cell per Newton iteration: 2N^2 + 20N (1200 at N = 20; the block inverse is
+    2N^2 of it)."""
     return 2.0 * N * N + 20.0 * N
 
 
-def factor_bytes_per_cell(N: int, factor_bytes: int) -> float:
-    """Algorithmic HBM bytes per cell of one factor/solve launch with stored block factors.
+def iteration_bytes_per_cell() -> float:
+    """Compulsory FP64 HBM bytes per cell per Newton iteration: read psi^n, psi, kappa_a, eta, kappa_s and
+    write the new psi (6 x 8 B).  Stored block factors are not algorithmic traffic: they are what a design
+    pays on top."""
+    return 48.0
 
-    Compulsory: read psi, kappa_a, eta, kappa_s and the residual, write the update (6 x 8 B).
-    Stored factors: C_i (N x N per zone, i.e. N values per cell) and y_i (1 per cell), each
-    written by the forward sweep and read back by the backward sweep.
-    """
-    return 48.0 + 2.0 * (N + 1) * factor_bytes
+
+def stored_factor_bytes_per_cell(N: int, factor_bytes: int) -> float:
+    """HBM bytes per cell of the stored block-Thomas factors: C_i (N values per cell) and y_i (one), written
+    by the forward sweep and read back by the backward sweep."""
+    return 2.0 * (N + 1) * factor_bytes
+
+
+def roofline_time(cells: int, N: int, mixed: bool) -> dict:
+    """T_roof = max(bytes / HBM, sum_p flops_p / peak_p) of one Newton iteration over `cells` cells.
+
+    FP64 path: all 2N^2 + 20N flops at the FP64 peak.  Mixed path: the block elimination (2N^2 + 10N,
+    1000 at N = 20) at the FP32 peak and the rest (10N, 200) at the FP64 peak."""
+    tot = iteration_flops_per_cell(N)
+    f32 = (2.0 * N * N + 10.0 * N) if mixed else 0.0
+    f64 = tot - f32
+    t_hbm = iteration_bytes_per_cell() * cells / (PEAK_HBM_GBS * 1e9)
+    t_alu = cells * (f32 / (PEAK_FP32_TFLOPS * 1e12) + f64 / (PEAK_FP64_TFLOPS * 1e12))
+    return dict(t_roof=max(t_hbm, t_alu), t_hbm=t_hbm, t_alu=t_alu, flops=tot * cells, flops_fp32=f32 * cells,
+                flops_fp64=f64 * cells, bytes=iteration_bytes_per_cell() * cells)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Cores this process may run on, at most 16 (the host share of one GPU on the benchmark machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def source_hash(path):
@@ -485,20 +526,35 @@ def main(argv=None):
 
     value = sum(u_m) / sum(t_m)
     ms = 1e3 * sum(t_m) / len(t_m)
-    flops_launch = factor_flops_per_cell(w.N) * cells
-    bytes_launch = factor_bytes_per_cell(w.N, 4) * cells
-    t_hbm, t_alu = bytes_launch / (PEAK_HBM_GBS * 1e9), flops_launch / (PEAK_VALU_TFLOPS * 1e12)
+    # roofline of one Newton iteration at the algorithmic count (48 B and 2N^2 + 20N flops per cell),
+    # charged to the dominant kernel (the float32 factor/solve launch) and to the whole step
+    rm = roofline_time(cells, w.N, mixed=True)
     kernel_src = os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_factor.hip")
     # the counters were taken on the full 16384-ray launch; a reduced run reports none
     tr = traffic_record(kernel_src) if rays is None else None
-    # the roofline time of the launch is max(HBM time, VALU time); with stored factors it is HBM
-    achieved = bytes_launch / t_fac / 1e9
-    roof = dict(bound="hbm" if t_hbm >= t_alu else "alu", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=achieved / PEAK_HBM_GBS, traffic=(tr or {}).get("bytes_per_launch"),
-                kernel="k_factor_f32<20>", kernel_ms=1e3 * t_fac,
-                algorithmic_bytes_per_launch=bytes_launch, flops_per_launch=flops_launch,
-                alu_tflops=flops_launch / t_fac / 1e12, alu_peak_tflops=PEAK_VALU_TFLOPS,
-                roofline_ms=1e3 * max(t_hbm, t_alu), residual_kernel_ms=1e3 * t_res)
+    traffic = (tr or {}).get("bytes_per_launch")
+    iters_mean = float(mixed_iters.mean())
+    if rm["t_alu"] >= rm["t_hbm"]:
+        # compute-bound: achieved flop rate against the blended peak of the FP32 and FP64 parts
+        peak = rm["flops"] / rm["t_alu"] / 1e12
+        roof = dict(bound="alu", achieved=rm["flops"] / t_fac / 1e12, peak=peak, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=rm["bytes"] / t_fac / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+    roof.update(frac=rm["t_roof"] / t_fac, traffic=traffic,
+                traffic_over_algorithmic=(traffic / rm["bytes"]) if traffic else None,
+                kernel=KERNEL_F32, kernel_ms=1e3 * t_fac, roofline_ms=1e3 * rm["t_roof"],
+                roofline_hbm_ms=1e3 * rm["t_hbm"], roofline_alu_ms=1e3 * rm["t_alu"],
+                algorithmic_bytes_per_launch=rm["bytes"], flops_per_launch=rm["flops"],
+                flops_fp32_per_launch=rm["flops_fp32"], flops_fp64_per_launch=rm["flops_fp64"],
+                peaks=dict(fp32_tflops=PEAK_FP32_TFLOPS, fp64_tflops=PEAK_FP64_TFLOPS, hbm_gbs=PEAK_HBM_GBS),
+                stored_factor_bytes_per_launch=stored_factor_bytes_per_cell(w.N, 4) * cells,
+                step_roofline_ms=1e3 * rm["t_roof"] * iters_mean, step_frac=(rm["t_roof"] * iters_mean) / (ms / 1e3),
+                residual_kernel_ms=1e3 * t_res)
+    if out_fp64 is not None:
+        rd = roofline_time(cells, w.N, mixed=False)
+        out_fp64["roofline"] = dict(kernel_frac=rd["t_roof"] / (out_fp64["factor_kernel_ms"] / 1e3),
+                                    roofline_ms=1e3 * rd["t_roof"],
+                                    step_frac=rd["t_roof"] * out_fp64["mean_iters"] / (out_fp64["ms_per_step"] / 1e3))
 
     wmeta = dict(name=w.name, R=w.R, I=w.I, N=w.N, S=w.S)
     multi = None
@@ -511,9 +567,9 @@ def main(argv=None):
     cpu = None
     if not a.no_cpu:
         log("CPU oracle baseline")
-        workers = min(16, os.cpu_count() or 1)
+        workers = host_cores()
         v, dt, nsys, upd = cpu_baseline(a.cpu_sample, workers)
-        cpu = dict(value=v, unit="updates/s", cores=workers, kind="oracle",
+        cpu = dict(value=v, unit="updates/s", cores=workers, kind="oracle", cpu_model=cpu_model(),
                    sample=f"{nsys} systems (species x rays spread over the 16384 rays) of the same workload, "
                           f"FP64 Newton to 1e-12, {upd} updates in {dt:.1f} s wall")
         if out_ye is not None:

@@ -192,6 +192,25 @@ tm_status tm_assemble(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
 tm_status tm_factor_solve(tm_ctx *ctx, const tm_inputs *in, const double *psi,
                           const double *rhs, double *x, int32_t transpose);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): tm_factor_solve with every internal buffer (grid constants,
+ * per-system scalars, the factor workspace) taken from one static device array of
+ * TM_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its load until the process ends.
+ * Calls no hipMalloc/hipFree and no allocating library routine, clears what must start at zero with
+ * kernels (no memset nodes), and never synchronises: the work is only enqueued on the context's stream.
+ * The factorisation runs in batches that fit the scratch; systems that trip the diagonal-pivot guard
+ * are re-factored with partial pivoting in the same enqueued sequence (TM_PIVOT=never is not honoured).
+ * flags (device, [S][R] int32, may be NULL) receives the per-system TM_FLAG_ZERO_PIVOT and
+ * TM_FLAG_PIVOT_FALLBACK bits; TM_ERR_SINGULAR is not returned (that would need a read-back).
+ * Returns TM_ERR_WORKSPACE, before any device work, when the per-system arrays (20 bytes per system)
+ * plus 16 slots of factors (I * NT * (NT+1) values each, float32 in TM_PREC_MIXED, else double)
+ * exceed the scratch; TM_ERR_INVALID_ARG as tm_factor_solve, and for a lapse (not supported here).
+ * Every call on one GPU shares that GPU's scratch array: calls that overlap in time on one GPU (two
+ * streams, two contexts, two threads) race and give wrong results.                          */
+#define TM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+tm_status tm_factor_solve_noalloc(tm_ctx *ctx, const tm_inputs *in, const double *psi,
+                                  const double *rhs, double *x, int32_t transpose, int32_t *flags);
+
 /* Backward-Euler Newton iteration (eq. a62aa) for psi^{n+1} of every system.
  * psi holds the initial guess on entry (usually a copy of psi_n) and psi^{n+1} on
  * return.  Per system, an update J delta = -G is applied while

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -377,6 +378,59 @@ tm_status check_zero_pivots(tm_ctx* c) {
     return TM_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free solve
+// One scratch array per device for tm_factor_solve_noalloc: grid constants, per-system scalars and the
+// factor workspace.  In host code `scratch` names a host-side stand-in, so kernels get the device
+// address taken once per device with hipGetSymbolAddress (each device holds its own copy).
+constexpr size_t kScratchBytes = TM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up on the device's first call).
+tm_status scratch_of(tm_ctx* c, unsigned char** out) {
+    if (c->device < 0 || c->device >= kMaxDevices) return set_err(c, TM_ERR_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        TM_TRY(hip_check(c, hipSetDevice(c->device), "hipSetDevice"));
+        void* ptr = nullptr;
+        TM_TRY(hip_check(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+        if (!ptr) return set_err(c, TM_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[c->device] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[c->device]);
+    return TM_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Layout of the scratch array for a problem; factor slots are what remains after the small arrays.
+struct ScratchPlan {
+    size_t o_consts, o_rmax, o_flags, o_guard, o_redo, o_count, o_ws;
+    long long batch;                       // systems per factor launch (0: does not fit)
+};
+
+ScratchPlan plan_scratch(const tm_problem& p) {
+    ScratchPlan pl{};
+    const long long ns = n_systems(p);
+    size_t o = 0;
+    pl.o_consts = o; o += align256(sizeof(tmk::Consts));
+    pl.o_rmax = o;   o += align256((size_t)ns * sizeof(double));
+    pl.o_flags = o;  o += align256((size_t)ns * sizeof(int));
+    pl.o_guard = o;  o += align256((size_t)ns * sizeof(int));
+    pl.o_redo = o;   o += align256((size_t)ns * sizeof(int));
+    pl.o_count = o;  o += 256;
+    pl.o_ws = o;
+    const size_t per = tmk::factor_ws_bytes_per_system(p.n_zones, p.n_groups, p.precision == TM_PREC_MIXED);
+    pl.batch = 0;
+    if (o < kScratchBytes && per > 0) {
+        const long long slots = (long long)((kScratchBytes - o) / per);
+        pl.batch = std::min(std::max(slots - tmk::kWsPadSystems, 0LL), ns);
+    }
+    return pl;
+}
+
 }  // namespace
 
 extern "C" {
@@ -530,6 +584,77 @@ tm_status tm_factor_solve(tm_ctx* c, const tm_inputs* in, const double* psi, con
     TM_TRY(run_factor(c, in, psi, rhs, 1.0, x, nullptr, nullptr, fp32, transpose != 0, nullptr,
                       fp32 ? c->res : nullptr));
     return check_zero_pivots(c);
+}
+
+tm_status tm_factor_solve_noalloc(tm_ctx* c, const tm_inputs* in, const double* psi, const double* rhs, double* x,
+                                  int32_t transpose, int32_t* flags) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    TM_TRY(check_inputs(c, in));
+    if (!psi || !rhs || !x) return set_err(c, TM_ERR_INVALID_ARG, "psi, rhs and x are required");
+    TM_TRY(no_lapse(c, in, "tm_factor_solve_noalloc"));
+    const ScratchPlan pl = plan_scratch(c->p);
+    if (pl.batch < 1)
+        return set_err(c, TM_ERR_WORKSPACE, "problem too large for the " + std::to_string(kScratchBytes >> 20) +
+                                                " MiB scratch of tm_factor_solve_noalloc (per-system arrays plus "
+                                                "one batch of factors must fit)");
+    unsigned char* base = nullptr;
+    TM_TRY(scratch_of(c, &base));
+    const long long ns = n_systems(c->p);
+    const bool fp32 = c->p.precision == TM_PREC_MIXED;
+    const int NT = tmk::padded_groups(c->p.n_groups);
+    const size_t es = fp32 ? 4 : 8;
+    tmk::Consts* cs = reinterpret_cast<tmk::Consts*>(base + pl.o_consts);
+    double* rmax = reinterpret_cast<double*>(base + pl.o_rmax);
+    int* fl = flags ? flags : reinterpret_cast<int*>(base + pl.o_flags);
+    int* guard = reinterpret_cast<int*>(base + pl.o_guard);
+    int* redo = reinterpret_cast<int*>(base + pl.o_redo);
+    int* count = reinterpret_cast<int*>(base + pl.o_count);
+    TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, c->p.n_groups, cs, c->stream), "setup kernel"));
+    // the scratch keeps the previous call's contents: flags and the guard start at zero
+    TM_TRY(hip_check(c, tmk::launch_fill_i32(fl, ns, 0, c->stream), "fill kernel"));
+    TM_TRY(hip_check(c, tmk::launch_fill_i32(guard, ns, 0, c->stream), "fill kernel"));
+    if (fp32)
+        TM_TRY(hip_check(c, tmk::launch_sys_absmax(rhs, ns, (long long)c->p.n_zones * c->p.n_groups, rmax, c->stream),
+                         "rhs scale kernel"));
+    tmk::FactorArgs a;
+    a.sh = shape_of(c->p);
+    a.f = fields_of(*in);
+    a.cs = cs;
+    a.psi = psi;
+    a.rhs = rhs;
+    a.rhs_sign = 1.0;
+    a.rhs_max = fp32 ? rmax : nullptr;
+    a.x = x;
+    a.psi_out = nullptr;
+    a.active = nullptr;
+    a.flags = fl;
+    a.iters = nullptr;
+    a.guard = guard;
+    a.growth_limit = c->growth_limit;
+    a.dx = nullptr;
+    a.pending = nullptr;
+    a.alpha = nullptr;
+    a.wsC = base + pl.o_ws;
+    a.wsY = base + pl.o_ws + (size_t)(pl.batch + tmk::kWsPadSystems) * c->p.n_zones * NT * NT * es;
+    const bool pivot_first = c->pivot_policy == 1;
+    for (long long s0 = 0; s0 < ns; s0 += pl.batch) {
+        a.sys0 = s0;
+        a.nsys = std::min(pl.batch, ns - s0);
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose != 0, pivot_first, c->stream), "factor kernel"));
+    }
+    if (!pivot_first) {
+        // no read-back: the partial-pivoting re-run is launched for the marked systems (waves without one
+        // return at once)
+        TM_TRY(hip_check(c, tmk::launch_mark(guard, ns, redo, count, c->stream), "mark kernel"));
+        a.active = redo;
+        for (long long s0 = 0; s0 < ns; s0 += pl.batch) {
+            a.sys0 = s0;
+            a.nsys = std::min(pl.batch, ns - s0);
+            TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose != 0, true, c->stream),
+                             "pivoting factor kernel"));
+        }
+    }
+    return TM_OK;
 }
 
 tm_status tm_newton_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, double* psi, int32_t max_iter,

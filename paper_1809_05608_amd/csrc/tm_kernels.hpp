@@ -92,6 +92,9 @@ hipError_t launch_count_active(const int* active, long long n, int* count, hipSt
 hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int* backtrack, double* alpha,
                             hipStream_t st);
 
+// p[0..n) = v (a kernel, so that a captured graph holds no memset node)
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
+
 // *count = number of entries j with (flags[j] & mask) != 0
 hipError_t launch_count_bits(const int* flags, long long n, int mask, int* count, hipStream_t st);
 

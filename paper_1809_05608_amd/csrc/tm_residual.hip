@@ -679,6 +679,19 @@ hipError_t launch_backtrack(const Shape& sh, double* psi, const double* dx, int*
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- fill (a kernel rather than a memset node)
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int* __restrict__ p, long long n, int v) {
+    const long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) p[j] = v;
+}
+
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- active-system count
 
 // max |v| over each system's cells (one block per system)

@@ -28,7 +28,7 @@ EADV_LAGRANGIAN, EADV_LAPSE = 0, 1
 EADV_FLAG_DISPLACEMENT, EADV_FLAG_OVERFILL, EADV_FLAG_OVERFILL_CLAMP = 1, 2, 4
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
-            "tm_factor_solve", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_workspace_bytes",
+            "tm_factor_solve", "tm_factor_solve_noalloc", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_workspace_bytes",
             "tm_ye_newton_step", "tm_temperature_update", "tm_energy_advect", "tm_status_string", "tm_last_error"]
 
 
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_set_workspace.argtypes = [V, V, ctypes.c_size_t]
     lib.tm_assemble.argtypes = [V, P(Inputs), V, V, V, V]
     lib.tm_factor_solve.argtypes = [V, P(Inputs), V, V, V, I32]
+    lib.tm_factor_solve_noalloc.argtypes = [V, P(Inputs), V, V, V, I32, V]
     lib.tm_newton_step.argtypes = [V, P(Inputs), V, V, I32, D, P(Stats)]
     lib.tm_adjoint_step.argtypes = [V, P(Inputs), V, V, V, V, V, V, V, V]
     lib.tm_luminosity_seed.argtypes = [V, P(Inputs), V, V]
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_last_error.argtypes = [V]
     lib.tm_last_error.restype = ctypes.c_char_p
     for name in ("tm_create", "tm_destroy", "tm_set_workspace", "tm_assemble", "tm_factor_solve",
+                 "tm_factor_solve_noalloc",
                  "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_newton_step",
                  "tm_temperature_update", "tm_energy_advect"):
         getattr(lib, name).restype = ctypes.c_int
@@ -237,6 +239,19 @@ class Context:
         inp = self._inputs(f)
         self._check(self.lib.tm_factor_solve(self._h, ctypes.byref(inp), _ptr(psi), _ptr(rhs), _ptr(x),
                                              int(bool(transpose))))
+
+    def factor_solve_noalloc(self, f: DeviceFields, psi, rhs, x, transpose=False, flags=None):
+        """tm_factor_solve_noalloc: the solve with the library's static scratch (no allocation, no
+        synchronisation); `flags` (int32 [S][R] on the device) receives the per-system flag bits."""
+        self._cell(psi, "psi"), self._cell(rhs, "rhs"), self._cell(x, "x")
+        if flags is not None:
+            p = self.problem
+            if (flags.dtype != torch.int32 or flags.device != self.device or not flags.is_contiguous()
+                    or tuple(flags.shape) != (p.n_species, p.n_rays)):
+                raise ValueError(f"flags must be a contiguous int32 tensor of shape {(p.n_species, p.n_rays)}")
+        inp = self._inputs(f)
+        self._check(self.lib.tm_factor_solve_noalloc(self._h, ctypes.byref(inp), _ptr(psi), _ptr(rhs), _ptr(x),
+                                                     int(bool(transpose)), _ptr(flags)))
 
     def newton_step(self, f: DeviceFields, psi_n, psi, max_iter: int, rtol: float, with_stats=True,
                     raise_on_status=True):

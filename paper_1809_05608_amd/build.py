@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_ye.hip", "tm_energy.hip"]
+SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_factor_q.hip", "tm_ye.hip", "tm_energy.hip"]
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -42,7 +42,10 @@ def flags():
 # Per-source extra flags.  The coupled-block elimination is a fully unrolled loop over up to 57 pivot
 # steps (a run-time step index would index the register-held row and move it to scratch); its size
 # exceeds the default limit of `#pragma unroll`, and a partly unrolled loop spills to scratch memory.
-EXTRA = {"tm_ye.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+EXTRA = {"tm_ye.hip": ["-mllvm", "-pragma-unroll-threshold=60000"],
+         # the quad factor kernel unrolls its 20-step elimination and zone assembly completely: a run-time
+         # step index would index the register-held rows and move them to scratch
+         "tm_factor_q.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
 
 
 def _compile(src: str, verbose: bool) -> str:

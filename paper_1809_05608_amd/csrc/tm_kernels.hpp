@@ -74,7 +74,10 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
 hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                          double* blocks, hipStream_t st);
 
-hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st);
+// quad = true: the float32 forward solve with diagonal pivots runs on the quad kernel (N <= 20)
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st,
+                         bool quad = true);
+bool launch_factor_quad(const FactorArgs& a, hipStream_t st);
 
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,

@@ -45,7 +45,7 @@ struct tm_ctx {
     // pivoting policy: 0 diagonal pivots with guarded fallback to partial pivoting (default),
     // 1 always partial pivoting, 2 diagonal pivots only (guard trips become failures)
     int pivot_policy = 0;
-    bool quad = true;           // float32 diagonal-pivot solve on the quad kernel (TM_FACTOR_KERNEL=lane: off)
+    int factor_kernel = tmk::kFactorQuadMfma;   // float32 diagonal-pivot solve: TM_FACTOR_KERNEL=mfma|valu|lane
     double growth_limit = 16.0;
     long long pivot_fallbacks = 0;   // systems re-factored with partial pivoting since creation
     // Y_e-coupled step, per ray [R] unless stated (allocated on first use)
@@ -343,7 +343,7 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     for (long long s0 = 0; s0 < ns; s0 += batch) {
         a.sys0 = s0;
         a.nsys = std::min(batch, ns - s0);
-        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, pivot_first, c->stream, c->quad), "factor kernel"));
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, pivot_first, c->stream, c->factor_kernel), "factor kernel"));
     }
     if (pivot_first) return TM_OK;
     // systems whose diagonal-pivot elimination tripped the growth guard were left untouched:
@@ -477,7 +477,11 @@ tm_status tm_create(const tm_problem* p, void* stream, tm_ctx** out) {
         else if (!std::strcmp(e, "never")) c->pivot_policy = 2;
     }
     if (const char* e = std::getenv("TM_GROWTH_LIMIT")) c->growth_limit = std::atof(e);
-    if (const char* e = std::getenv("TM_FACTOR_KERNEL")) c->quad = std::strcmp(e, "lane") != 0;
+    if (const char* e = std::getenv("TM_FACTOR_KERNEL")) {
+        if (!std::strcmp(e, "lane")) c->factor_kernel = tmk::kFactorLane;
+        else if (!std::strcmp(e, "valu")) c->factor_kernel = tmk::kFactorQuadValu;
+        else if (!std::strcmp(e, "mfma")) c->factor_kernel = tmk::kFactorQuadMfma;
+    }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return TM_ERR_HIP;
@@ -642,7 +646,7 @@ tm_status tm_factor_solve_noalloc(tm_ctx* c, const tm_inputs* in, const double* 
     for (long long s0 = 0; s0 < ns; s0 += pl.batch) {
         a.sys0 = s0;
         a.nsys = std::min(pl.batch, ns - s0);
-        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose != 0, pivot_first, c->stream, c->quad), "factor kernel"));
+        TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose != 0, pivot_first, c->stream, c->factor_kernel), "factor kernel"));
     }
     if (!pivot_first) {
         // no read-back: the partial-pivoting re-run is launched for the marked systems (waves without one

@@ -582,10 +582,12 @@ static void launch_nt(const FactorArgs& a, bool fp32, bool tr, bool pv, hipStrea
     else launch_tp<double, NT>(a, tr, pv, st);
 }
 
-hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st, bool quad) {
+hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st, int kernel) {
     // the float32 forward solve with diagonal pivots (the mixed-precision Newton update) takes one
     // system per quad of lanes up to 20 groups
-    if (quad && fp32 && !transpose && !pivot && launch_factor_quad(a, st)) return hipGetLastError();
+    if (kernel != kFactorLane && fp32 && !transpose && !pivot &&
+        launch_factor_quad(a, st, kernel == kFactorQuadMfma))
+        return hipGetLastError();
     switch (padded_groups(a.sh.N)) {
         case 4: launch_nt<4>(a, fp32, transpose, pivot, st); break;
         case 8: launch_nt<8>(a, fp32, transpose, pivot, st); break;

@@ -26,6 +26,8 @@ namespace tmk {
 
 namespace {
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // Broadcast lane P of every quad to the quad's four lanes.
 template <int P>
 __device__ __forceinline__ float qbc(float x) {
@@ -119,7 +121,7 @@ constexpr int kQuadSystems = 16;        // systems per wavefront
 // Workspace of the quad kernel, per wave group of 16 systems and zone: C as R * NT runs of 64 floats
 // (entry j of lane l's row slot s at [s NT + j][l]), then y as R runs of 64 floats.  A group takes
 // 16 * NT * (NT + 1) floats per zone, the same as 16 slots of the one-row-per-lane layout.
-template <int NT, bool LAPSE>
+template <int NT, bool LAPSE, bool MF>
 __global__ __launch_bounds__(kQuadBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_factor_q(FactorArgs A) {
     constexpr int R = NT / 4;              // rows per lane
@@ -199,13 +201,16 @@ void k_factor_q(FactorArgs A) {
 
 
     // ---------------------------------------------------------------- forward sweep
-    float a[R][NT];                    // rows of the block: C_{i-1} on entry to a zone, then Ahat_i
+    // rows of the block (C_{i-1} on entry to a zone, then Ahat_i) as float4 runs of columns: entry (s, j)
+    // is a4[s][j / 4][j % 4], and each run is one 4x4 accumulator tile of the matrix-core update
+    v4f a4[R][NT / 4];
+#define AE(s_, j_) a4[s_][(j_) >> 2][(j_) & 3]
     float g[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) {
         s_y[s][lane] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) a[s][j] = 0.0f;
+        for (int j = 0; j < NT; ++j) AE(s, j) = 0.0f;
     }
     // derivatives of the flux through the zone's lower edge, carried from the previous zone in LDS
     // rather than in registers (one wavefront per workgroup: [which][row slot][lane])
@@ -338,7 +343,7 @@ void k_factor_q(FactorArgs A) {
             s_psi[s][lane] = (float)psi_c;
             // Schur update: row k of -diag(bm) C_{i-1}, right-hand side minus bm y_{i-1}
 #pragma unroll
-            for (int j = 0; j < NT; ++j) a[s][j] = -bm * a[s][j];
+            for (int j = 0; j < NT; ++j) AE(s, j) = -bm * AE(s, j);
             g[s] = real ? (float)(s_rs[0][lane] * ah.rhs[s]) : 0.0f;
             g[s] = fmaf(-bm, s_y[s][lane], g[s]);
             fence_sched();
@@ -377,7 +382,7 @@ void k_factor_q(FactorArgs A) {
                     const float ps = s_psi[s][lane];
                     const float w = up ? ps : 1.0f - ps;
                     const float v = up ? 1.0f - pb : pb;
-                    a[s][kp] = fmaf(ca * P, fmaf(w, tM, 1.0f), a[s][kp]);
+                    AE(s, kp) = fmaf(ca * P, fmaf(w, tM, 1.0f), AE(s, kp));
                     ds[s] = fmaf(P, fmaf(v, tM, 1.0f), ds[s]);
                 }
                 fence_sched();
@@ -389,7 +394,7 @@ void k_factor_q(FactorArgs A) {
 #pragma unroll
         for (int s = 0; s < R; ++s)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[s][4 * s + t] += (q == t) ? s_dg[s][lane] : 0.0f;
+            for (int t = 0; t < 4; ++t) AE(s, 4 * s + t) += (q == t) ? s_dg[s][lane] : 0.0f;
         fence_sched();
 
         // ---- in-place Gauss-Jordan with diagonal pivots: step cc eliminates with row cc, held by lane
@@ -401,39 +406,62 @@ void k_factor_q(FactorArgs A) {
         for (int cc = 0; cc < NT; ++cc) {
             const int p = cc % 4, sp = cc / 4;
             const bool own = q == p;
-            const float piv = qbc(a[sp][cc], p);
+            const float piv = qbc(AE(sp, cc), p);
             const float pinv = frcp(piv);
             pv[sp] = own ? piv : pv[sp];
             float f[R];
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                f[s] = a[s][cc] * pinv;
+                f[s] = AE(s, cc) * pinv;
                 if (s == sp) f[s] = own ? 0.0f : f[s];
                 gmax = fmaxf(gmax, fabsf(f[s]));
             }
+            if constexpr (MF) {
+                // rank-1 update on the matrix cores: tile (s, t) holds entries (4s + q, 4t + i) in register i
+                // of lane q, so v_mfma_f32_4x4x1f32 (one 4x4 block per quad) with A = the pivot row's entry
+                // 4t + i from lane i and B = -f of the lane's own row adds -f_r u_c to every entry.  Lane i
+                // takes entry 4t + i of the broadcast pivot row (a 4-way select on the quad lane).
+                const bool q1 = q & 1, q2 = q & 2;
+                float nf[R];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                if (j == cc) continue;
-                const float u = qbc(a[sp][j], p);
+                for (int s2 = 0; s2 < R; ++s2) nf[s2] = -f[s2];
+                // tiles in the order the next step needs them: the one holding column cc + 1 (the next
+                // multipliers and pivot) first
 #pragma unroll
-                for (int s = 0; s < R; ++s) a[s][j] = fmaf(-f[s], u, a[s][j]);
-                if (j % 4 == 3) fence_sched();     // a few pivot-row values in flight at a time
+                for (int tt = 0; tt < NT / 4; ++tt) {
+                    const int t = ((cc + 1) / 4 + tt) % (NT / 4);
+                    const float b0 = qbc(AE(sp, 4 * t), p), b1 = qbc(AE(sp, 4 * t + 1), p);
+                    const float b2 = qbc(AE(sp, 4 * t + 2), p), b3 = qbc(AE(sp, 4 * t + 3), p);
+                    const float ut = q2 ? (q1 ? b3 : b2) : (q1 ? b1 : b0);
+#pragma unroll
+                    for (int s2 = 0; s2 < R; ++s2) a4[s2][t] = __builtin_amdgcn_mfma_f32_4x4x1f32(ut, nf[s2], a4[s2][t], 0, 0, 0);
+                    if (tt % 2 == 1) fence_sched();    // a few pivot-row tiles in flight at a time
+                }
+            } else {
+                // columns in the order the next step needs them: column cc + 1 (the next multipliers and
+                // pivot) first, so that the next step's pivot chain can overlap this step's tail
+#pragma unroll
+                for (int jj = 1; jj < NT; ++jj) {
+                    const int j = (cc + jj) % NT;
+                    const float u = qbc(AE(sp, j), p);
+#pragma unroll
+                    for (int s = 0; s < R; ++s) AE(s, j) = fmaf(-f[s], u, AE(s, j));
+                }
             }
             const float ug = qbc(g[sp], p);
 #pragma unroll
             for (int s = 0; s < R; ++s) g[s] = fmaf(-f[s], ug, g[s]);
             const float bpiv = s_bp[sp][(lane & ~3) + p];
 #pragma unroll
-            for (int s = 0; s < R; ++s) a[s][cc] = -f[s] * bpiv;
-            a[sp][cc] = own ? bpiv : a[sp][cc];
-            fence_sched();
+            for (int s = 0; s < R; ++s) AE(s, cc) = -f[s] * bpiv;
+            AE(sp, cc) = own ? bpiv : AE(sp, cc);
         }
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             zp |= !(fabsf(pv[s]) > 0.0f) || !isfinite(pv[s]);
             const float ip = frcp(pv[s]);
 #pragma unroll
-            for (int j = 0; j < NT; ++j) a[s][j] *= ip;
+            for (int j = 0; j < NT; ++j) AE(s, j) *= ip;
             g[s] *= ip;
             s_y[s][lane] = g[s];
         }
@@ -445,7 +473,7 @@ void k_factor_q(FactorArgs A) {
 #pragma unroll
             for (int s = 0; s < R; ++s)
 #pragma unroll
-                for (int j = 0; j < NT; ++j) at(qc + (s * NT + j) * 64, wl1) = a[s][j];
+                for (int j = 0; j < NT; ++j) at(qc + (s * NT + j) * 64, wl1) = AE(s, j);
             float* qy = uniform_ptr(wsY + (size_t)i * kQuadSystems * NT);
 #pragma unroll
             for (int s = 0; s < R; ++s) at(qy + s * 64, wl1) = g[s];
@@ -550,14 +578,20 @@ void k_factor_q(FactorArgs A) {
 
 // Launch of the quad kernel for the float32 forward solve with diagonal pivots (NT <= 20); returns
 // false when the shape is not covered (the caller then uses the one-row-per-lane kernel).
-bool launch_factor_quad(const FactorArgs& a, hipStream_t st) {
+bool launch_factor_quad(const FactorArgs& a, hipStream_t st, bool mfma) {
     const unsigned blocks = (unsigned)((a.nsys + kQuadSystems - 1) / kQuadSystems);
     const bool lp = a.f.lapse != nullptr;
     switch (padded_groups(a.sh.N)) {
+#define TM_QUAD_LAUNCH(NTV, LP, MFV) hipLaunchKernelGGL((k_factor_q<NTV, LP, MFV>), dim3(blocks), dim3(kQuadBlock), 0, st, a)
 #define TM_QUAD_CASE(NTV)                                                                                  \
     case NTV:                                                                                              \
-        if (lp) hipLaunchKernelGGL((k_factor_q<NTV, true>), dim3(blocks), dim3(kQuadBlock), 0, st, a);     \
-        else hipLaunchKernelGGL((k_factor_q<NTV, false>), dim3(blocks), dim3(kQuadBlock), 0, st, a);       \
+        if (lp) {                                                                                          \
+            if (mfma) TM_QUAD_LAUNCH(NTV, true, true);                                                     \
+            else TM_QUAD_LAUNCH(NTV, true, false);                                                         \
+        } else {                                                                                           \
+            if (mfma) TM_QUAD_LAUNCH(NTV, false, true);                                                    \
+            else TM_QUAD_LAUNCH(NTV, false, false);                                                        \
+        }                                                                                                  \
         return true;
         TM_QUAD_CASE(4)
         TM_QUAD_CASE(8)
@@ -565,6 +599,7 @@ bool launch_factor_quad(const FactorArgs& a, hipStream_t st) {
         TM_QUAD_CASE(16)
         TM_QUAD_CASE(20)
 #undef TM_QUAD_CASE
+#undef TM_QUAD_LAUNCH
         default: return false;
     }
 }

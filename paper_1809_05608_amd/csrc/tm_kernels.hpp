@@ -74,10 +74,13 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
 hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                          double* blocks, hipStream_t st);
 
-// quad = true: the float32 forward solve with diagonal pivots runs on the quad kernel (N <= 20)
+// The float32 forward solve with diagonal pivots (N <= 20) runs on one system per quad of lanes:
+// kFactorQuadMfma with the elimination's rank-1 updates on the matrix cores, kFactorQuadValu on the
+// vector units; kFactorLane keeps one row per lane.
+enum FactorKernel : int { kFactorLane = 0, kFactorQuadValu = 1, kFactorQuadMfma = 2 };
 hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st,
-                         bool quad = true);
-bool launch_factor_quad(const FactorArgs& a, hipStream_t st);
+                         int kernel = kFactorQuadMfma);
+bool launch_factor_quad(const FactorArgs& a, hipStream_t st, bool mfma);
 
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,

@@ -510,8 +510,13 @@ def luminosity_seed(sys: System, shape) -> np.ndarray:
 
 # ---------------------------------------------------------------- adjoint
 
-def adjoint(sys: System, psi: np.ndarray, seed: np.ndarray) -> np.ndarray:
-    """mu solving J(psi)^T mu = seed through the dense transpose (numpy.linalg.solve)."""
+def adjoint(sys: System, psi: np.ndarray, seed: np.ndarray, solver: str = "dense") -> np.ndarray:
+    """mu solving J(psi)^T mu = seed: through the dense transpose (numpy.linalg.solve), or with
+    solver="block" by the transposed block-Thomas elimination (the same system; the block route is
+    pinned to the dense one, and serves full-size rays where a dense 10^4-square solve is slow)."""
+    if solver == "block":
+        blocks, bm, bp = jacobian_blocks(sys, psi)
+        return block_thomas_solve(blocks, bm, bp, seed, transpose=True)
     return dense_solve(sys, psi, seed, transpose=True)
 
 
@@ -593,7 +598,7 @@ def multistep_objective(systems: list, psis: list) -> float:
     return float(sum(luminosity(sy, p) for sy, p in zip(systems, psis)))
 
 
-def multistep_adjoint(systems: list, psis: list):
+def multistep_adjoint(systems: list, psis: list, solver: str = "dense"):
     """Reverse recursion for J = sum_s L_N(psi^s).
 
     With lambda_s the total derivative of J with respect to psi^s,
@@ -606,7 +611,7 @@ def multistep_adjoint(systems: list, psis: list):
     mu_next = np.zeros_like(psis[0])
     for s in range(S - 1, -1, -1):
         seed = luminosity_seed(systems[s], psis[s].shape) + mu_next
-        mu = adjoint(systems[s], psis[s], seed)
+        mu = adjoint(systems[s], psis[s], seed, solver=solver)
         grads[s] = param_vjp(systems[s], psis[s], mu)
         mu_next = mu
     return mu_next, grads

@@ -207,3 +207,84 @@ def test_multistep_checkpointed_adjoint_matches_oracle():
                 np.testing.assert_allclose(grads[s][sp, r], go[s]["kappa_a"], rtol=1e-8,
                                            atol=1e-11 * np.max(np.abs(go[s]["kappa_a"])))
     ctx.close()
+
+
+def test_cfg4_ten_steps_mixed_equals_fp64_and_adjoint_equals_oracle():
+    """The benchmark's multi-step job at full size: 16384 rays x 540 zones x 20 groups x 4 species, ten
+    drifting steps.  The FP64 path runs the ten steps to 1e-12 with one checkpoint per step; the mixed
+    path runs them from the same psi^0 (psi carried over) and must equal the FP64 state of every step on
+    every cell within 1e-8 (tau metric).  The checkpointed FP64 adjoint of J = sum_s L_N(psi^s) over the
+    ten steps must give, on two sampled systems (an electron-neutrino and a heavy-antineutrino ray), the
+    oracle's dJ/dpsi^0 and per-step kappa_a gradients from its own ten-step forward and reverse recursion
+    (eq. a62 objective)."""
+    steps, R = 10, 16384
+    sampled = [(0, 1234), (3, 15001)]
+    dev = torch.device("cuda")
+    held = {}
+
+    def fields_at(s):
+        if held.get("s") != s:
+            held.clear()
+            held["w"] = synth.make(4, step=s, device=dev)
+            held["s"] = s
+        return tm.DeviceFields.of(held["w"])
+
+    w0 = synth.make(4, step=0, device=dev)
+    psi0 = w0.psi_n.clone()
+    prob = tm.problem_of(w0, tm.PREC_FP64)
+    prob_m = tm.problem_of(w0, tm.PREC_MIXED)
+    del w0
+    cps = [torch.empty_like(psi0) for _ in range(steps)]
+    say("case cfg4 ten steps: FP64 forward")
+    ctx = tm.Context(prob)
+    _, st64 = multistep.forward(ctx, fields_at, psi0, steps, max_iter=30, rtol=1e-12, checkpoints=cps)
+    for s, st in enumerate(st64):
+        assert int(st["flags"].max().item()) == 0, s
+    ctx.close()
+    _release()
+    say("  mixed forward, compared with the FP64 state of every step")
+    ctx = tm.Context(prob_m)
+    prev = psi0
+    cur = torch.empty_like(psi0)
+    worst = 0.0
+    for s in range(steps):
+        f = fields_at(s)
+        cur.copy_(prev)
+        st, stats = ctx.newton_step(f, prev, cur, 30, 1e-12, raise_on_status=False)
+        assert st == 0, (s, tm.STATUS_NAMES[st])
+        err = float(torch.max((cur - cps[s]).abs() / cps[s].abs().clamp_min(TAU)).item())
+        say(f"  step {s}: mixed vs FP64 {err:.3e}, mean updates {float(stats['iters'].double().mean()):.2f}")
+        worst = max(worst, err)
+        if s == 0:
+            prev = torch.empty_like(psi0)
+        prev.copy_(cur)
+    assert worst < 1e-8
+    del prev, cur
+    ctx.close()
+    _release()
+    say("  checkpointed FP64 adjoint")
+    ctx = tm.Context(prob)
+    grads = {}
+
+    def on_grad(s, mu, g):
+        grads[s] = {sr: g["kappa_a"][sr[0], sr[1]].cpu().numpy() for sr in sampled}
+
+    d0 = multistep.adjoint(ctx, fields_at, psi0, cps, on_grad=on_grad)
+    d0s = {sr: d0[sr[0], sr[1]].cpu().numpy() for sr in sampled}
+    states = {sr: [cps[s][sr[0], sr[1]].cpu().numpy() for s in range(steps)] for sr in sampled}
+    ctx.close()
+    held.clear()
+    del cps, d0
+    _release()
+    for sp, r in sampled:
+        say(f"  oracle ten-step forward and reverse recursion, species {sp} ray {r}")
+        W = [synth.make(4, rays=[r], step=s).numpy() for s in range(steps)]
+        syss = [oracle.systems_from_workload(w)[sp][0] for w in W]
+        psis = oracle.multistep_forward(syss, W[0]["psi_n"][sp, 0], max_iter=30, rtol=1e-12)
+        for s in range(steps):
+            assert rel_err(states[(sp, r)][s], psis[s]) < 1e-12, (sp, r, s)
+        g0, go = oracle.multistep_adjoint(syss, psis, solver="block")
+        np.testing.assert_allclose(d0s[(sp, r)], g0, rtol=1e-9, atol=1e-12 * np.max(np.abs(g0)))
+        for s in range(steps):
+            np.testing.assert_allclose(grads[s][(sp, r)], go[s]["kappa_a"], rtol=1e-8,
+                                       atol=1e-11 * np.max(np.abs(go[s]["kappa_a"])))

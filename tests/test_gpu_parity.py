@@ -183,6 +183,40 @@ def test_mixed_precision_refines_to_fp64_answer():
     assert np.all(stats["res_inf"] <= 1e-10 * stats["res0_inf"])
 
 
+@pytest.mark.parametrize("kernel", ["mfma", "valu", "lane"])
+@pytest.mark.parametrize("shape", [dict(S=2, R=9, I=31, N=20), dict(S=1, R=17, I=12, N=13), dict(S=3, R=2, I=5, N=3),
+                                   dict(S=1, R=33, I=7, N=8)])
+def test_float32_factor_kernels_agree_with_oracle(monkeypatch, shape, kernel):
+    """The three float32 diagonal-pivot factor kernels (one system per quad with the rank-1 updates on the
+    matrix cores or on the vector units, one row per lane): standalone solves within the float32 bar
+    of the oracle's block-Thomas solve, and the mixed Newton step refined to 1e-12 within the mixed bar
+    of the FP64 oracle; system counts that leave partial quads and wave groups."""
+    monkeypatch.setenv("TM_FACTOR_KERNEL", kernel)
+    say("case f32 kernel", kernel, shape)
+    w = synth.make_custom(**shape)
+    rng = np.random.default_rng(7)
+    psi = w.psi_n.numpy() * 1.03
+    rhs = rng.standard_normal(psi.shape)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd, tm.PREC_MIXED)
+    x = torch.empty(psi.shape, dtype=torch.float64, device="cuda")
+    ctx.factor_solve(f, torch.as_tensor(psi, device="cuda"), torch.as_tensor(rhs, device="cuda"), x, False)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    syss = oracle.systems_from_workload(w.numpy())
+    for s in range(w.S):
+        for r in range(w.R):
+            A, bm, bp = oracle.jacobian_blocks(syss[s][r], psi[s, r])
+            xo = oracle.block_thomas_solve(A, bm, bp, rhs[s, r])
+            assert np.max(np.abs(x[s, r] - xo)) / np.max(np.abs(xo)) < 3e-4, (s, r)
+    pd = wd.psi_n.clone()
+    st, stats = ctx.newton_step(f, wd.psi_n, pd, 30, 1e-12, raise_on_status=False)
+    torch.cuda.synchronize()
+    assert st == 0, tm.STATUS_NAMES[st]
+    ref, _ = oracle_newton(w, 30, 1e-12)
+    assert rel_err(pd.cpu().numpy(), ref) < MIXED_BAR
+
+
 # ------------------------------------------------------------------ adjoint
 
 def _adjoint_workload():

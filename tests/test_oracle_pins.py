@@ -367,6 +367,21 @@ def test_pins_catch_transposed_nes_jacobian(monkeypatch):
         test_jacobian_matches_central_differences(1)
 
 
+def test_block_route_of_the_multistep_adjoint_equals_the_dense_route():
+    """The transposed block-Thomas route of the reverse recursion (used on full-size rays) gives the dense
+    route's dJ/dpsi^0 and per-step opacity gradients."""
+    ws = [synth.make(4, rays=[3], zones=20, groups=8, species=2, step=s).numpy() for s in range(3)]
+    for sp in range(2):
+        syss = [oracle.systems_from_workload(w)[sp][0] for w in ws]
+        psis = oracle.multistep_forward(syss, ws[0]["psi_n"][sp, 0], max_iter=10, rtol=0.0)
+        g_d, gr_d = oracle.multistep_adjoint(syss, psis)
+        g_b, gr_b = oracle.multistep_adjoint(syss, psis, solver="block")
+        np.testing.assert_allclose(g_b, g_d, rtol=1e-10, atol=1e-13 * np.max(np.abs(g_d)))
+        for a, b in zip(gr_b, gr_d):
+            for n in ("kappa_a", "eta", "kappa_s"):
+                np.testing.assert_allclose(a[n], b[n], rtol=1e-9, atol=1e-12 * np.max(np.abs(b[n])))
+
+
 def test_multistep_adjoint_matches_central_differences():
     """Three drifting steps, J = sum_s L(psi^s): the reverse recursion equals central differences of J
     with respect to psi^0 and to the absorption opacity of the first and last step."""

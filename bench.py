@@ -35,7 +35,7 @@ TAU = 1e-30
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_F32 = "k_factor_f32<20>"
+KERNEL_F32 = "k_factor_q<20, false, true>"
 
 
 def log(*a):
@@ -210,9 +210,20 @@ def multistep_leg(tm, torch, synth, dev, rays, steps, rtol, max_iter):
     ctx.close()
     torch.cuda.empty_cache()
     log(f"  forward: {steps} steps in {1e3 * t_fwd:.0f} ms (generation {1e3 * gen[0]:.0f} ms excluded)")
-    gen[0] = 0.0
     ctx = tm.Context(prob_d)
     batch = prealloc_workspace(torch, ctx)
+    # The FP64 plain path over the same steps (psi carried over on its own), each step's state compared
+    # with the mixed checkpoint on every cell (tau metric); untimed.
+    prev, cur, vs64 = psi0.clone(), torch.empty_like(psi0), []
+    for s in range(steps):
+        f = fields_at(s)
+        cur.copy_(prev)
+        ctx.newton_step(f, prev, cur, max_iter, rtol)
+        vs64.append(rel_err_gpu(cps[s], cur))
+        prev, cur = cur, prev
+    del prev, cur
+    log("  mixed vs FP64 per step: " + " ".join(f"{e:.1e}" for e in vs64))
+    gen[0] = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     d0 = multistep.adjoint(ctx, fields_at, psi0, cps)
@@ -227,7 +238,8 @@ def multistep_leg(tm, torch, synth, dev, rays, steps, rtol, max_iter):
     torch.cuda.empty_cache()
     return dict(steps=steps, forward_ms=1e3 * t_fwd, adjoint_ms=1e3 * t_adj,
                 forward_updates_per_s=updates / t_fwd, mean_iters_per_step=iters,
-                adjoint_precision="fp64", adjoint_factor_batch=batch, checkpoints=steps, gradient_finite=finite)
+                mixed_vs_fp64_per_step=vs64, adjoint_precision="fp64", adjoint_factor_batch=batch,
+                checkpoints=steps, gradient_finite=finite)
 
 
 def ye_factor_flops_per_zone(N: int) -> float:
@@ -529,7 +541,7 @@ def main(argv=None):
     # roofline of one Newton iteration at the algorithmic count (48 B and 2N^2 + 20N flops per cell),
     # charged to the dominant kernel (the float32 factor/solve launch) and to the whole step
     rm = roofline_time(cells, w.N, mixed=True)
-    kernel_src = os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_factor.hip")
+    kernel_src = os.path.join(ROOT, "paper_1809_05608_amd", "csrc", "tm_factor_q.hip")
     # the counters were taken on the full 16384-ray launch; a reduced run reports none
     tr = traffic_record(kernel_src) if rays is None else None
     traffic = (tr or {}).get("bytes_per_launch")

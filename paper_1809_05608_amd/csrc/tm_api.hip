@@ -45,7 +45,7 @@ struct tm_ctx {
     // pivoting policy: 0 diagonal pivots with guarded fallback to partial pivoting (default),
     // 1 always partial pivoting, 2 diagonal pivots only (guard trips become failures)
     int pivot_policy = 0;
-    int factor_kernel = tmk::kFactorQuadMfma;   // float32 diagonal-pivot solve: TM_FACTOR_KERNEL=mfma|valu|lane
+    int factor_kernel = tmk::kFactorQuadMfma;   // float32 diagonal-pivot solve: TM_FACTOR_KERNEL=window|bf16x3|bf16|mfma|valu|lane
     double growth_limit = 16.0;
     long long pivot_fallbacks = 0;   // systems re-factored with partial pivoting since creation
     // Y_e-coupled step, per ray [R] unless stated (allocated on first use)
@@ -481,6 +481,9 @@ tm_status tm_create(const tm_problem* p, void* stream, tm_ctx** out) {
         if (!std::strcmp(e, "lane")) c->factor_kernel = tmk::kFactorLane;
         else if (!std::strcmp(e, "valu")) c->factor_kernel = tmk::kFactorQuadValu;
         else if (!std::strcmp(e, "mfma")) c->factor_kernel = tmk::kFactorQuadMfma;
+        else if (!std::strcmp(e, "window")) c->factor_kernel = tmk::kFactorQuadWindow;
+        else if (!std::strcmp(e, "bf16x3")) c->factor_kernel = tmk::kFactorQuadBf16x3;
+        else if (!std::strcmp(e, "bf16")) c->factor_kernel = tmk::kFactorQuadBf16;
     }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

@@ -23,6 +23,7 @@ struct Consts {
     double W[kMaxN];
     double de[kMaxN];
     double P[kMaxN][kMaxN];
+    int nes_window;   // 1 when every group energy is at least 1.25 times the one below it
 };
 
 struct Shape {

@@ -586,7 +586,7 @@ hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pi
     // the float32 forward solve with diagonal pivots (the mixed-precision Newton update) takes one
     // system per quad of lanes up to 20 groups
     if (kernel != kFactorLane && fp32 && !transpose && !pivot &&
-        launch_factor_quad(a, st, kernel == kFactorQuadMfma))
+        launch_factor_quad(a, st, kernel))
         return hipGetLastError();
     switch (padded_groups(a.sh.N)) {
         case 4: launch_nt<4>(a, fp32, transpose, pivot, st); break;

@@ -27,6 +27,7 @@ namespace tmk {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // Broadcast lane P of every quad to the quad's four lanes.
 template <int P>
@@ -121,9 +122,36 @@ constexpr int kQuadSystems = 16;        // systems per wavefront
 // Workspace of the quad kernel, per wave group of 16 systems and zone: C as R * NT runs of 64 floats
 // (entry j of lane l's row slot s at [s NT + j][l]), then y as R runs of 64 floats.  A group takes
 // 16 * NT * (NT + 1) floats per zone, the same as 16 slots of the one-row-per-lane layout.
-template <int NT, bool LAPSE, bool MF>
+// Splits x into bf16 parts: x = hi + lo up to 2^-17 |x| (NB = 3), or hi alone (NB = 1).  The matrix-core
+// products from the parts are hi hi (NB = 1), or hi hi + hi lo + lo hi (NB = 3, about float32 accuracy:
+// the lo lo term is below 2^-16 relative).
+template <int NB>
+__device__ __forceinline__ void bf16_parts(const float (&x)[8], bf8& hi, bf8& lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        hi[e] = (__bf16)x[e];
+        if constexpr (NB == 3) lo[e] = (__bf16)(x[e] - (float)hi[e]);
+    }
+}
+// Forms of the float32 NES block (template argument NES):
+//   kNesExp2    entries and diagonal sums on the vector units, one exp2 per entry;
+//   kNesWindow  the detailed-balance factor as row and column scalings inside an energy window (two
+//               exp2 per row instead of one per entry), entries and diagonal sums on the vector units;
+//   kNesBf16, kNesBf16x3  the window scalings for the entries, and the diagonal sums as bf16 matrix-core
+//               contractions with float32 accumulation, one bf16 product per term or three (hi/lo parts).
+enum NesForm : int { kNesExp2 = 0, kNesWindow = 1, kNesBf16 = 2, kNesBf16x3 = 3 };
+
+template <int NT, bool LAPSE, bool MF, int NES>
 __global__ __launch_bounds__(kQuadBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_factor_q(FactorArgs A) {
+    // the windowed form runs on energy grids that admit it (checked by the setup kernel); a launch of the
+    // exp2 form beside it takes the other grids
+    constexpr int NB = NES == kNesBf16 ? 1 : NES == kNesBf16x3 ? 3 : 0;   // bf16 products per term
+    if constexpr (NES != kNesExp2) {
+        if (A.cs->nes_window == 0) return;
+    } else {
+        if (A.skip_if_window && A.cs->nes_window != 0) return;
+    }
     constexpr int R = NT / 4;              // rows per lane
     constexpr int PS = NT + 4;             // LDS row stride of the NES shape (float4 aligned)
     __shared__ __align__(16) float s_P[NT * PS];
@@ -184,7 +212,9 @@ void k_factor_q(FactorArgs A) {
     // LDS with the other per-lane values that the zone loops read but registers need not hold
     __shared__ double s_rs[2][kQuadBlock];
     __shared__ float s_y[R][kQuadBlock];              // y_{i-1} of the lane's rows
-    __shared__ float s_dg[R][kQuadBlock], s_bp[R][kQuadBlock], s_psi[R][kQuadBlock];
+    __shared__ __align__(16) float s_dg[R][kQuadBlock];
+    __shared__ __align__(16) float s_psi[R][kQuadBlock];
+    __shared__ float s_bp[R][kQuadBlock];
     {
         double rs_in = A.rhs_sign, rs_out = 1.0;
         if (A.rhs_max) {
@@ -219,6 +249,105 @@ void k_factor_q(FactorArgs A) {
     for (int s = 0; s < R; ++s) s_dh[0][s][lane] = s_dh[1][s][lane] = 0.0f;
     float gmax = 0.0f;                 // largest |multiplier| (growth guard)
     bool zp = false;                   // a zero or non-finite pivot met
+
+    // bf16 matrix-core form of the NES diagonal sums (NB > 0).  With U and L the strict upper and lower
+    // triangles of the shape matrix P (the same for every zone and system), the diagonal sum of row k is
+    //   ds_k = [U psi + L (1 - psi)]_k + Ei_k [U (E (1 - psi))]_k + E_k [L (Ei psi)]_k,
+    // products of one constant 32 x 32 matrix with a column per system: v_mfma_f32_16x16x32_bf16 with
+    // the wave's 16 systems as the 16 columns (A: lane i + 16 h holds row i, entries 8h..8h+7; B: lane
+    // j + 16 h holds rows 8h..8h+7 of column j; C: lane j + 16 h holds rows 4h..4h+3 of column j).  The
+    // columns are read from the quads' LDS rows ([k / 4][4 j + k % 4]: four consecutive rows of a system
+    // are one float4), and each output lane adds -ca_j ds to the diagonal of its four rows in LDS.
+    __shared__ __align__(16) float s_E[NES ? R : 1][kQuadBlock];
+    __shared__ __align__(16) float s_Ei[NES ? R : 1][kQuadBlock];
+    __shared__ float s_ca[kQuadSystems];
+    auto nes_diagonal_mfma = [&]() {
+        if constexpr (NB > 0) {
+            // lane id from an opaque source, so that the operands built from it (the A tiles are the same
+            // in every zone) are rebuilt per zone instead of being hoisted and held through the zone loop
+            int l;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+            const int j = l & 15, h = l >> 4;
+            // rows 8h..8h+7 of column j: two float4 of the LDS rows, zero beyond the last row slot
+            auto column = [&](const float (*arr)[kQuadBlock], float (&v)[8]) {
+                const bool ok0 = 2 * h < R, ok1 = 2 * h + 1 < R;
+                const v4f a = *reinterpret_cast<const v4f*>(&arr[ok0 ? 2 * h : 0][4 * j]);
+                const v4f b = *reinterpret_cast<const v4f*>(&arr[ok1 ? 2 * h + 1 : 0][4 * j]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = ok0 ? a[e] : 0.0f;
+                    v[4 + e] = ok1 ? b[e] : 0.0f;
+                }
+            };
+            constexpr int MT = (NT + 15) / 16;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int i = 16 * mt + j;                   // row of the A tile held by this lane
+                const int slot = 4 * mt + h;                 // row slot of the C rows held by this lane
+#pragma unroll
+                for (int tri = 0; tri < 2; ++tri) {          // U, then L
+#pragma unroll
+                    for (int prod = 0; prod < 2; ++prod) {
+                        // prod 0: U psi or L (1 - psi); prod 1: U (E (1 - psi)) or L (Ei psi), scaled by the
+                        // row's Ei or E.  Each product is folded into the diagonal before the next starts, and
+                        // with NB = 3 the bf16 parts of A are taken one at a time (part 0: hi against both
+                        // parts of the column, part 1: lo against its hi part), so few registers are live.
+                        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                        for (int part = 0; part < (NB == 3 ? 2 : 1); ++part) {
+                            bf8 at8, bh, bl;
+                            {
+                                // A: row i of the triangle, entries 8h..8h+7 (a clamped read is masked)
+                                const int ic = i < NT ? i : NT - 1, k0 = 8 * h < PS - 8 ? 8 * h : PS - 8;
+                                const v4f pa = *reinterpret_cast<const v4f*>(&s_P[ic * PS + k0]);
+                                const v4f pb = *reinterpret_cast<const v4f*>(&s_P[ic * PS + k0 + 4]);
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) {
+                                    const int kk = 8 * h + e;
+                                    const bool in = i < NT && kk < NT && (tri == 0 ? kk > i : kk < i);
+                                    const float v = in ? (e < 4 ? pa[e] : pb[e - 4]) : 0.0f;
+                                    const __bf16 hi = (__bf16)v;
+                                    at8[e] = part == 0 ? hi : (__bf16)(v - (float)hi);
+                                }
+                            }
+                            float b8[8];
+                            column(s_psi, b8);
+                            if (prod == 0) {
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) b8[e] = tri == 0 ? b8[e] : 1.0f - b8[e];
+                            } else {
+                                float x8[8];
+                                column(tri == 0 ? s_E : s_Ei, x8);
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) b8[e] = x8[e] * (tri == 0 ? 1.0f - b8[e] : b8[e]);
+                            }
+                            bf16_parts<NB>(b8, bh, bl);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(at8, bh, acc, 0, 0, 0);
+                            if (NB == 3 && part == 0) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(at8, bl, acc, 0, 0, 0);
+                            fence_sched();
+                        }
+                        // C: rows 16 mt + 4h .. +3 of system j
+                        if (slot < R) {
+                            v4f* dg = reinterpret_cast<v4f*>(&s_dg[slot][4 * j]);
+                            const float nca = -s_ca[j];
+                            v4f d = *dg;
+                            if (prod == 0) {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) d[r] = fmaf(nca, acc[r], d[r]);
+                            } else {
+                                const v4f sc = *reinterpret_cast<const v4f*>(tri == 0 ? &s_Ei[slot][4 * j]
+                                                                                     : &s_E[slot][4 * j]);
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) d[r] = fmaf(nca * sc[r], acc[r], d[r]);
+                            }
+                            *dg = d;
+                        }
+                        fence_sched();
+                    }
+                }
+            }
+        }
+    };
 
     // Software pipeline over zones: the cell values a zone's assembly needs are loaded into registers one
     // zone ahead (issued before the previous zone's elimination and factor stores, so that waiting for
@@ -280,9 +409,10 @@ void k_factor_q(FactorArgs A) {
         r1 = at(re, gz.rb + 8u);
         if (LAPSE) e0 = at(uniform_ptr(A.f.lapse_edge), gz.rb);
     }
-    Ahead ah = fetch(0);
+    Ahead ah;                          // zone 0's values are loaded at the top of its iteration
 
     for (int i = 0; i < I; ++i) {
+        if (i == 0) ah = fetch(0);
         const LaneGeo gz = geo();
         const int q = gz.q;
         const uint32_t wl1 = gz.wl;
@@ -353,8 +483,37 @@ void k_factor_q(FactorArgs A) {
         r1 = ah.r2;
         if (LAPSE) e0 = ah.ae;
         wave_sync();                   // the quad's row values in LDS are read by the other lanes below
+        if constexpr (NES != kNesExp2) {
+            // window scalings (and the matrix-core NES diagonal sums), before the next zone's loads take
+            // their registers
+            if (nes) {
+                // Energy window of the system: the groups with x = eps log2(e) / T within 200 of group 0.
+                // Inside it M = 2^-|x_k - x_k'| is the product of the scalings E = 2^(xm - x) and
+                // Ei = 2^(x - xm), xm = x_0 + 100 (both within 2^+-100).  Any pair with a member outside
+                // has |x_k - x_k'| >= 200 (1 - eps_{k-1}/eps_k), at least 40 when adjacent groups differ
+                // by 25% (the setup kernel checks the grid; on other grids the exp2 form runs), so
+                // M < 2^-40 there and is taken as 0.
+                const float xs = (float)(1.4426950408889634 * drcp1(Tz));
+                const float x0 = s_eps[0] * xs, xm = x0 + 100.0f;
+#pragma unroll
+                for (int s = 0; s < R; ++s) {
+                    const float x = s_eps[4 * s + q] * xs;
+                    const bool w = (4 * s + q < N) && (x - x0 <= 200.0f);
+                    s_E[s][lane] = w ? __builtin_amdgcn_exp2f(xm - x) : 0.0f;
+                    s_Ei[s][lane] = w ? __builtin_amdgcn_exp2f(x - xm) : 0.0f;
+                }
+                if constexpr (NB > 0) {
+                    if (q == 0) s_ca[lane >> 2] = (float)(-c * ampz);
+                    wave_sync();
+                    nes_diagonal_mfma();
+                    wave_sync();
+                }
+                fence_sched();
+            }
+        }
         // the next zone's values are requested now, ahead of this zone's elimination and factor stores
-        if (i + 1 < I) ah = fetch(i + 1);
+        // (the windowed form after its NES entries, which then have the registers to themselves)
+        if (NES == kNesExp2 && i + 1 < I) ah = fetch(i + 1);
 
         // ---- NES block: -c dt [(1 - psi_k) K^in_{kk'} + psi_k K^out_{kk'}] off the diagonal, and the
         //      diagonal sum c dt sum_k' [K^in psi_k' + K^out (1 - psi_k')].  With M = exp(-|eps_k - eps_k'|/T)
@@ -363,32 +522,72 @@ void k_factor_q(FactorArgs A) {
         if (nes) {
             const float ca = (float)(-c * ampz);
             const float xs = (float)(1.4426950408889634 * drcp1(Tz));  // log2 e / T
-            float xl[R], ds[R];
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-                xl[s] = s_eps[4 * s + q] * xs;
-                ds[s] = 0.0f;
-            }
-#pragma unroll
-            for (int kp = 0; kp < NT; ++kp) {
-                const float xb = qbc(xl[kp / 4], kp % 4);
-                const float pb = s_psi[kp / 4][(lane & ~3) + kp % 4];
+            if constexpr (NES == kNesExp2) {
+                float xl[R], ds[R];
 #pragma unroll
                 for (int s = 0; s < R; ++s) {
-                    const float P = s_P[(4 * s + q) * PS + kp];
-                    const float d = xb - xl[s];                    // > 0 above the diagonal
-                    const float tM = __builtin_amdgcn_exp2f(-fabsf(d)) - 1.0f;
-                    const bool up = d > 0.0f;
-                    const float ps = s_psi[s][lane];
-                    const float w = up ? ps : 1.0f - ps;
-                    const float v = up ? 1.0f - pb : pb;
-                    AE(s, kp) = fmaf(ca * P, fmaf(w, tM, 1.0f), AE(s, kp));
-                    ds[s] = fmaf(P, fmaf(v, tM, 1.0f), ds[s]);
+                    xl[s] = s_eps[4 * s + q] * xs;
+                    ds[s] = 0.0f;
                 }
-                fence_sched();
-            }
 #pragma unroll
-            for (int s = 0; s < R; ++s) s_dg[s][lane] = fmaf(-ca, ds[s], s_dg[s][lane]);
+                for (int kp = 0; kp < NT; ++kp) {
+                    const float xb = qbc(xl[kp / 4], kp % 4);
+                    const float pb = s_psi[kp / 4][(lane & ~3) + kp % 4];
+#pragma unroll
+                    for (int s = 0; s < R; ++s) {
+                        const float P = s_P[(4 * s + q) * PS + kp];
+                        const float d = xb - xl[s];                    // > 0 above the diagonal
+                        const float tM = __builtin_amdgcn_exp2f(-fabsf(d)) - 1.0f;
+                        const bool up = d > 0.0f;
+                        const float ps = s_psi[s][lane];
+                        const float w = up ? ps : 1.0f - ps;
+                        const float v = up ? 1.0f - pb : pb;
+                        AE(s, kp) = fmaf(ca * P, fmaf(w, tM, 1.0f), AE(s, kp));
+                        ds[s] = fmaf(P, fmaf(v, tM, 1.0f), ds[s]);
+                    }
+                    fence_sched();
+                }
+#pragma unroll
+                for (int s = 0; s < R; ++s) s_dg[s][lane] = fmaf(-ca, ds[s], s_dg[s][lane]);
+            } else {
+                // entries with M from the energy-window scalings (and, in the matrix-core forms, the diagonal
+                // sums already formed above)
+                float E[R], Ei[R], ds[R];                    // this zone's scalings, from LDS
+#pragma unroll
+                for (int s = 0; s < R; ++s) {
+                    E[s] = s_E[s][lane];
+                    Ei[s] = s_Ei[s][lane];
+                    ds[s] = 0.0f;
+                }
+#pragma unroll
+                for (int kp = 0; kp < NT; ++kp) {
+                    const float eb = qbc(E[kp / 4], kp % 4), eib = qbc(Ei[kp / 4], kp % 4);
+                    const float pb = NES == kNesWindow ? s_psi[kp / 4][(lane & ~3) + kp % 4] : 0.0f;
+#pragma unroll
+                    for (int s = 0; s < R; ++s) {
+                        const int k = 4 * s + q;
+                        const float P = s_P[k * PS + kp];
+                        const bool up = kp > k;
+                        const float tM = (up ? eb * Ei[s] : E[s] * eib) - 1.0f;
+                        const float ps = s_psi[s][lane];
+                        const float w = up ? ps : 1.0f - ps;
+                        AE(s, kp) = fmaf(ca * P, fmaf(w, tM, 1.0f), AE(s, kp));
+                        if constexpr (NES == kNesWindow) {
+                            const float v = up ? 1.0f - pb : pb;
+                            ds[s] = fmaf(P, fmaf(v, tM, 1.0f), ds[s]);
+                        }
+                    }
+                    fence_sched();
+                }
+                if constexpr (NES == kNesWindow) {
+#pragma unroll
+                    for (int s = 0; s < R; ++s) s_dg[s][lane] = fmaf(-ca, ds[s], s_dg[s][lane]);
+                }
+            }
+        }
+        if (NES != kNesExp2 && i + 1 < I) {
+            fence_sched();
+            ah = fetch(i + 1);
         }
         // the diagonal: entry (k, k) of slot s sits in column 4s + q, one of the four columns 4s..4s+3
 #pragma unroll
@@ -577,21 +776,32 @@ void k_factor_q(FactorArgs A) {
 }
 
 // Launch of the quad kernel for the float32 forward solve with diagonal pivots (NT <= 20); returns
-// false when the shape is not covered (the caller then uses the one-row-per-lane kernel).
-bool launch_factor_quad(const FactorArgs& a, hipStream_t st, bool mfma) {
+// false when the shape is not covered (the caller then uses the one-row-per-lane kernel).  A windowed
+// NES form is launched together with the exp2 form of the same elimination, which runs instead of it
+// on energy grids that do not admit the window (the setup kernel's flag decides on the device).
+bool launch_factor_quad(const FactorArgs& a, hipStream_t st, int kernel) {
     const unsigned blocks = (unsigned)((a.nsys + kQuadSystems - 1) / kQuadSystems);
     const bool lp = a.f.lapse != nullptr;
+    FactorArgs ax = a;
+    ax.skip_if_window = 1;
     switch (padded_groups(a.sh.N)) {
-#define TM_QUAD_LAUNCH(NTV, LP, MFV) hipLaunchKernelGGL((k_factor_q<NTV, LP, MFV>), dim3(blocks), dim3(kQuadBlock), 0, st, a)
-#define TM_QUAD_CASE(NTV)                                                                                  \
-    case NTV:                                                                                              \
-        if (lp) {                                                                                          \
-            if (mfma) TM_QUAD_LAUNCH(NTV, true, true);                                                     \
-            else TM_QUAD_LAUNCH(NTV, true, false);                                                         \
-        } else {                                                                                           \
-            if (mfma) TM_QUAD_LAUNCH(NTV, false, true);                                                    \
-            else TM_QUAD_LAUNCH(NTV, false, false);                                                        \
-        }                                                                                                  \
+#define TM_QUAD_LAUNCH(NTV, LP, MFV, NESV, ARGS) \
+    hipLaunchKernelGGL((k_factor_q<NTV, LP, MFV, NESV>), dim3(blocks), dim3(kQuadBlock), 0, st, ARGS)
+#define TM_QUAD_WIN(NTV, LP, NESV)                   \
+    TM_QUAD_LAUNCH(NTV, LP, false, NESV, a);         \
+    TM_QUAD_LAUNCH(NTV, LP, false, kNesExp2, ax);
+#define TM_QUAD_LP(NTV, LP)                                                        \
+    switch (kernel) {                                                              \
+        case kFactorQuadMfma: TM_QUAD_LAUNCH(NTV, LP, true, kNesExp2, a); break;   \
+        case kFactorQuadValu: TM_QUAD_LAUNCH(NTV, LP, false, kNesExp2, a); break;  \
+        case kFactorQuadBf16x3: TM_QUAD_WIN(NTV, LP, kNesBf16x3) break;            \
+        case kFactorQuadBf16: TM_QUAD_WIN(NTV, LP, kNesBf16) break;                \
+        default: TM_QUAD_WIN(NTV, LP, kNesWindow) break;                           \
+    }
+#define TM_QUAD_CASE(NTV)             \
+    case NTV:                         \
+        if (lp) TM_QUAD_LP(NTV, true) \
+        else TM_QUAD_LP(NTV, false)   \
         return true;
         TM_QUAD_CASE(4)
         TM_QUAD_CASE(8)
@@ -599,6 +809,8 @@ bool launch_factor_quad(const FactorArgs& a, hipStream_t st, bool mfma) {
         TM_QUAD_CASE(16)
         TM_QUAD_CASE(20)
 #undef TM_QUAD_CASE
+#undef TM_QUAD_LP
+#undef TM_QUAD_WIN
 #undef TM_QUAD_LAUNCH
         default: return false;
     }

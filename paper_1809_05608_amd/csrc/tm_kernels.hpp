@@ -63,6 +63,8 @@ struct FactorArgs {
     void* wsY;                // [batch][I][NT]
     long long sys0;           // first system of the batch
     long long nsys;           // systems in the batch
+    int skip_if_window = 0;   // quad kernel, exp2 NES form: do nothing when the energy grid admits the
+                              // windowed form (launched beside the windowed kernel)
 };
 
 hipError_t launch_setup(const double* e_edge, const double* nes_g, int N, Consts* out, hipStream_t st);
@@ -74,13 +76,23 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
 hipError_t launch_blocks(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                          double* blocks, hipStream_t st);
 
-// The float32 forward solve with diagonal pivots (N <= 20) runs on one system per quad of lanes:
-// kFactorQuadMfma with the elimination's rank-1 updates on the matrix cores, kFactorQuadValu on the
-// vector units; kFactorLane keeps one row per lane.
-enum FactorKernel : int { kFactorLane = 0, kFactorQuadValu = 1, kFactorQuadMfma = 2 };
+// The float32 forward solve with diagonal pivots (N <= 20) runs on one system per quad of lanes.  Its
+// elimination updates run on the vector units, or on the matrix cores (kFactorQuadMfma); its NES block
+// takes one exp2 per entry (kFactorQuadValu, kFactorQuadMfma) or the energy-window scalings, with the
+// diagonal sums on the vector units (kFactorQuadWindow) or as bf16 matrix-core contractions with float32
+// accumulation in three bf16 products per term (kFactorQuadBf16x3) or one (kFactorQuadBf16).
+// kFactorLane keeps one row per lane.
+enum FactorKernel : int {
+    kFactorLane = 0,
+    kFactorQuadValu = 1,
+    kFactorQuadMfma = 2,
+    kFactorQuadWindow = 3,
+    kFactorQuadBf16x3 = 4,
+    kFactorQuadBf16 = 5
+};
 hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st,
                          int kernel = kFactorQuadMfma);
-bool launch_factor_quad(const FactorArgs& a, hipStream_t st, bool mfma);
+bool launch_factor_quad(const FactorArgs& a, hipStream_t st, int kernel);
 
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,

@@ -35,6 +35,11 @@ __global__ void k_setup(const double* __restrict__ e_edge, const double* __restr
         out->W[t] = t < N ? W[t] : 0.0;
         out->de[t] = (t + 1 < N) ? eps[t + 1] - eps[t] : 0.0;
     }
+    if (t == 0) {
+        int ok = 1;
+        for (int k = 1; k < N; ++k) ok &= eps[k] >= 1.25 * eps[k - 1];
+        out->nes_window = ok;
+    }
     for (int idx = t; idx < kMaxN * kMaxN; idx += blockDim.x) {
         const int k = idx / kMaxN, kp = idx % kMaxN;
         double v = 0.0;

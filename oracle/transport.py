@@ -6,7 +6,8 @@ Notation follows the paper (CHIMERA, arXiv 1809.05608):
   lambda   transport mean free path (eq. a17), 1/lambda = kappa_a + eta + kappa_s
            (absorption plus emission inverse mean free paths, eq. d10, plus the
            isoenergetic scattering opacity, eq. d8c)
-  F        flux limiter F_intrp (eq. a20)
+  F        flux limiter: F_intrp (eq. a20), or min(F_intrp, F_geom) (eqs. a23-a26a)
+  R_nu     neutrinosphere radius of a group (eqs. a23, a25, a62af)
   V_i, A   zone volume and edge area with the common 4*pi dropped and Gamma = 1
   eps_k    group-centre energies (eq. a01), W_k = eps_k^2 d eps_k (eq. a01b)
 The lapse a is 1 (no lapse input), so E = eps (eq. a8a).
@@ -21,9 +22,19 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
     so that eq. a01b holds.
   * the limiter's psi in eq. a20 is the edge mean (psi_i + psi_{i+1})/2, floored
     at psi_floor; |d psi/dR| uses the same one-sided difference as eq. a59.
-  * only F_intrp is used (F_geom needs a neutrinosphere radius, eq. a23-a26a).
-  * the outer boundary is free streaming, psi^(1) = psi^(0) of the last zone
-    (the limit of eq. a22), or zero flux; the inner boundary has zero flux.
+  * limiter 1 is F_intrp alone; limiter 2 is F = min(F_intrp, F_geom) (eq. a26a) with R_nu(eps_k)
+    an input.  In F_geom (eq. a23) the comoving limb cosine is the fixed-frame one (beta = 0 in eq.
+    a24: the transport step takes no matter velocity) without ray bending (G = 1 in eq. a26: no
+    gravitational mass is an input), psi^(0) at the edge is the same floored edge mean as in F_intrp,
+    and R is the edge radius; inside the neutrinosphere (R <= R_nu) F_geom = 1.
+  * outer boundary 1 is free streaming, psi^(1) = psi^(0) of the last zone (the limit of eq. a22);
+    outer boundary 2 is the paper's constant-luminosity condition (eq. a62af) with the neutrinosphere
+    radius squared (the printed 1/4 R_nu is read as 1/4 R_nu^2, the first-order form of
+    (1 + mu_nu) R^2 / 2): a ghost zone I+1 centred at the mirror of the last zone's centre across the
+    outer edge, holding psi_{I+1} = psi_I (R_I^2 - R_nu^2/4) / (R_{I+1}^2 - R_nu^2/4) (the ratio
+    clipped to [0, 1]), with the last zone's mean free path; the outer flux is then the ordinary
+    limited edge flux of eq. a59 between zone I and the ghost.  Boundary 0 is zero flux; the inner
+    boundary has zero flux.
   * NES enters moment 0 through the Phi_0 terms only and is excluded from the
     transport opacity, so the off-diagonal radial blocks stay diagonal (eq. a62ae).
   * the NES kernel obeys the in/out symmetry (eq. d3) in the weighted discrete
@@ -45,6 +56,9 @@ TERM_DIFFUSION = 1
 TERM_EMABS = 2
 TERM_NES = 4
 
+LIMITER_NONE, LIMITER_INTRP, LIMITER_GEOM = 0, 1, 2
+BC_ZERO_FLUX, BC_FREE_STREAM, BC_GEOMETRIC = 0, 1, 2
+
 
 @dataclasses.dataclass
 class System:
@@ -65,6 +79,7 @@ class System:
     psi_floor: float = 1e-300
     lapse: Optional[np.ndarray] = None        # [I] lapse a_i at zone centres (None: a = 1)
     lapse_edge: Optional[np.ndarray] = None   # [I+1] lapse at zone edges
+    r_nu: Optional[np.ndarray] = None         # [N] neutrinosphere radius R_nu(eps_k), cm (limiter 2, outer_bc 2)
 
     @property
     def I(self) -> int:
@@ -88,7 +103,8 @@ def systems_from_workload(w: dict) -> List[List[System]]:
                 inner_bc=w["inner_bc"], outer_bc=w["outer_bc"], terms=w["terms"],
                 limiter=w["limiter"], psi_floor=w["psi_floor"],
                 lapse=w["lapse"][r] if w.get("lapse") is not None else None,
-                lapse_edge=w["lapse_edge"][r] if w.get("lapse_edge") is not None else None))
+                lapse_edge=w["lapse_edge"][r] if w.get("lapse_edge") is not None else None,
+                r_nu=w["r_nu"][s] if w.get("r_nu") is not None else None))
         out.append(row)
     return out
 
@@ -136,13 +152,27 @@ def nes_kernels(amp: float, T: float, eps: np.ndarray, W: np.ndarray, G: np.ndar
     return k_out, k_in
 
 
-def edge_flux(u, v, lam, D, floor, limiter=1):
-    """Flux H = psi^(1) at an interior edge and its partial derivatives.
+def limb_factor(R, r_nu):
+    """(1 + mu_nu)/2 at radius R for neutrinosphere radii r_nu [N] (eqs. a24-a26 with beta = 0 and
+    G = 1): mu_nu = sqrt(1 - (R_nu/R)^2).  NaN where R <= R_nu (no geometric limit inside the
+    neutrinosphere, F_geom = 1)."""
+    r_nu = np.asarray(r_nu, dtype=np.float64)
+    out = np.full(r_nu.shape, np.nan)
+    outside = R > r_nu
+    out[outside] = 0.5 * (1.0 + np.sqrt(1.0 - (r_nu[outside] / R) ** 2))
+    return out
+
+
+def edge_flux(u, v, lam, D, floor, limiter=1, limb=None):
+    """Flux H = psi^(1) at an edge and its partial derivatives.
 
     eq. a59 with the limiter of eq. a20 (Gamma = 1):
         H = -(lam/3) F (v - u)/D,   F = [1 + lam |v - u| / (3 D m)]^{-1},
         m = max((u + v)/2, floor)
-    i.e. H = -lam m (v - u) / (3 D m + lam |v - u|).  With limiter=0, F = 1.
+    i.e. H = -lam m (v - u) / (3 D m + lam |v - u|).  With limiter=0, F = 1.  With limiter=2,
+    F = min(F_intrp, F_geom) (eq. a26a), F_geom = limb m / ((1/3) lam |v - u| / D) (eq. a23) where
+    limb = (1 + mu_nu)/2 is finite (outside the neutrinosphere) and F_geom = 1 elsewhere; where
+    F_geom is the smaller, H = -limb m sign(v - u) (eq. a26b), independent of lam.
     Returns H, dH/du, dH/dv, dH/dlam (arrays over groups).
     """
     delta = v - u
@@ -162,7 +192,38 @@ def edge_flux(u, v, lam, D, floor, limiter=1):
     dH_du = -dH_ddelta + 0.5 * dH_dm
     dH_dv = dH_ddelta + 0.5 * dH_dm
     dH_dlam = -3.0 * D * delta * r * r
+    if limiter == 2:
+        if limb is None:
+            raise ValueError("limiter 2 needs the neutrinosphere radii")
+        limb = np.broadcast_to(np.asarray(limb, dtype=np.float64), np.shape(H))
+        ad = np.abs(delta)
+        F_intrp = 3.0 * D * m / den
+        with np.errstate(divide="ignore", invalid="ignore"):
+            F_geom = np.where(np.isfinite(limb) & (ad > 0), limb * m / (lam * ad / (3.0 * D)), 1.0)
+        F = np.minimum(F_intrp, F_geom)
+        geom = F_geom < F_intrp
+        sgn = np.sign(delta)
+        H = np.where(geom, -lam / 3.0 * F * delta / D, H)
+        g = np.where(geom, limb, 0.0)
+        dH_du = np.where(geom, -0.5 * g * sgn * above, dH_du)
+        dH_dv = np.where(geom, -0.5 * g * sgn * above, dH_dv)
+        dH_dlam = np.where(geom, 0.0, dH_dlam)
     return H, dH_du, dH_dv, dH_dlam
+
+
+def outer_ghost(sys: System):
+    """Ghost zone of the geometric outer boundary (eq. a62af with R_nu^2): its centre R_{I+1}, the ratio
+    psi_{I+1}/psi_I = (R_I^2 - R_nu^2/4) / (R_{I+1}^2 - R_nu^2/4) per group (clipped to [0, 1]), and the
+    distance D = R_{I+1} - R_I of the outer edge."""
+    if sys.r_nu is None:
+        raise ValueError("the geometric outer boundary needs the neutrinosphere radii")
+    Rc = geometry(sys.r_edge)[0]
+    R_I = Rc[-1]
+    R_g = 2.0 * sys.r_edge[-1] - R_I
+    q = 0.25 * np.asarray(sys.r_nu, dtype=np.float64) ** 2
+    den = R_g ** 2 - q
+    ratio = np.where(den > 0, np.clip((R_I ** 2 - q) / np.where(den > 0, den, 1.0), 0.0, 1.0), 0.0)
+    return R_g, ratio, R_g - R_I
 
 
 def lapse_factors(sys: System):
@@ -201,14 +262,23 @@ def _edge_fluxes(sys: System, psi: np.ndarray):
     dHv = np.zeros((I + 1, N))
     dHl = np.zeros((I + 1, N))
     lam_e = np.zeros((I + 1, N))
+    def limb(e):
+        return limb_factor(sys.r_edge[e], sys.r_nu) if sys.limiter == LIMITER_GEOM else None
+
     for e in range(1, I):                            # edge e = i + 1/2 between zones e-1 and e
         lam_e[e] = np.sqrt(lam[e - 1] * lam[e])     # geometric mean, stated after eq. a59
         H[e], dHu[e], dHv[e], dHl[e] = edge_flux(psi[e - 1], psi[e], lam_e[e], D[e - 1],
-                                                 sys.psi_floor, sys.limiter)
+                                                 sys.psi_floor, sys.limiter, limb(e))
     # inner boundary: zero flux (H[0] = 0).  Outer boundary:
-    if sys.outer_bc == 1:
+    if sys.outer_bc == BC_FREE_STREAM:
         H[I] = psi[I - 1]                            # free streaming, psi^(1) = psi^(0)
         dHu[I] = 1.0
+    elif sys.outer_bc == BC_GEOMETRIC:               # ghost zone of eq. a62af
+        _, ratio, D_out = outer_ghost(sys)
+        lam_e[I] = lam[I - 1]
+        H[I], du, dv, dHl[I] = edge_flux(psi[I - 1], ratio * psi[I - 1], lam_e[I], D_out,
+                                         sys.psi_floor, sys.limiter, limb(I))
+        dHu[I] = du + ratio * dv                     # the ghost value moves with psi_I
     return H, dHu, dHv, dHl, lam_e
 
 
@@ -476,8 +546,8 @@ def step_stats(sys: System, psi_n: np.ndarray, psi: np.ndarray) -> dict:
     q_n = float(sys.c_dt * np.sum(VW * a[:, None] * (sys.eta * (1.0 - psi) - sys.kappa_a * psi))) \
         if sys.terms & TERM_EMABS else 0.0
     nes_n = float(sys.c_dt * np.sum(VW * a[:, None] * nes_source(sys, psi))) if sys.terms & TERM_NES else 0.0
-    if sys.terms & TERM_DIFFUSION and sys.outer_bc == 1:
-        h_out = psi[I - 1]
+    if sys.terms & TERM_DIFFUSION and sys.outer_bc != BC_ZERO_FLUX:
+        h_out = _edge_fluxes(sys, psi)[0][I]
     else:
         h_out = np.zeros(N)
     b_n = float(sys.c_dt * A[I] * np.sum(W * h_out))
@@ -492,19 +562,25 @@ def luminosity(sys: System, psi: np.ndarray) -> float:
     _, A, _ = _weights(sys)
     _, W = group_energies(sys.e_edge)
     I = psi.shape[0]
-    if not (sys.terms & TERM_DIFFUSION) or sys.outer_bc != 1:
+    if not (sys.terms & TERM_DIFFUSION) or sys.outer_bc == BC_ZERO_FLUX:
         return 0.0
-    return float(C_LIGHT * A[I] * np.sum(W * psi[I - 1]))
+    return float(C_LIGHT * A[I] * np.sum(W * _edge_fluxes(sys, psi)[0][I]))
 
 
-def luminosity_seed(sys: System, shape) -> np.ndarray:
-    """dL_N/dpsi as a cell array: nonzero only in the outermost zone."""
+def luminosity_seed(sys: System, shape, psi: Optional[np.ndarray] = None) -> np.ndarray:
+    """dL_N/dpsi as a cell array: nonzero only in the outermost zone.  The outer flux of the free-streaming
+    boundary is psi_I itself; that of the geometric boundary depends on psi_I through the limited flux
+    to the ghost zone, so its derivative needs the state psi."""
     _, A, _ = _weights(sys)
     _, W = group_energies(sys.e_edge)
     I, N = shape
     seed = np.zeros((I, N))
-    if (sys.terms & TERM_DIFFUSION) and sys.outer_bc == 1:
+    if (sys.terms & TERM_DIFFUSION) and sys.outer_bc == BC_FREE_STREAM:
         seed[I - 1] = C_LIGHT * A[I] * W
+    elif (sys.terms & TERM_DIFFUSION) and sys.outer_bc == BC_GEOMETRIC:
+        if psi is None:
+            raise ValueError("the geometric outer boundary's seed depends on psi")
+        seed[I - 1] = C_LIGHT * A[I] * W * _edge_fluxes(sys, psi)[1][I]
     return seed
 
 
@@ -544,6 +620,9 @@ def param_vjp(sys: System, psi: np.ndarray, mu: np.ndarray) -> dict:
             for zone in (e - 1, e):
                 dlam_dchi = -0.5 * lam_e[e] * lam[zone]
                 g_chi[zone] += w * dHl[e] * dlam_dchi
+        # the geometric outer boundary's flux carries the last zone's mean free path (lam_e = lam_I)
+        w_out = c * A[I] * mu[I - 1] / V[I - 1]
+        g_chi[I - 1] += w_out * dHl[I] * (-lam[I - 1] * lam[I - 1])
     g_ka = g_chi.copy()
     g_eta = g_chi.copy()
     g_ks = g_chi.copy()

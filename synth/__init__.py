@@ -6,6 +6,6 @@ consume the arrays it produces.
 """
 from .workload import (  # noqa: F401
     C_LIGHT, SEED, TERM_DIFFUSION, TERM_EMABS, TERM_NES, TERMS_ALL,
-    BC_ZERO_FLUX, BC_FREE_STREAM, CONFIGS, Workload, make, make_custom, YeInputs, ye_inputs, EadvInputs,
+    BC_ZERO_FLUX, BC_FREE_STREAM, BC_GEOMETRIC, LIMITER_NONE, LIMITER_INTRP, LIMITER_GEOM, R_NU_CM, CONFIGS, Workload, make, make_custom, YeInputs, ye_inputs, EadvInputs,
     eadv_inputs,
 )

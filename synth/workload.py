@@ -23,7 +23,10 @@ Recipe (one workload = S species x R rays x I zones x N groups):
 * NES-like kernel: amplitude a = 1e-7 (rho/1e14) cm^-1 per zone and a symmetric
   Gaussian G[k][k'] = exp(-(ln eps_k - ln eps_k')^2 / (2 * 0.3^2));
 * initial state psi^n = 0.9 f_FD(eps; mu, T);
-* c*dt with dt = 1e-6 s.
+* c*dt with dt = 1e-6 s;
+* neutrinosphere radius R_nu(eps) = 3e6 cm (eps / 10 MeV)^0.5 for every species (the radius at which the
+  Eddington-factor stand-in of the energy-advection inputs turns over); used only by the geometric
+  flux limiter and the geometric outer boundary (off by default).
 
 Extras per configuration: opacity spikes on 5% of the rays (stress case) and a
 smooth 1% per-step drift of rho and T (multi-step case).
@@ -51,6 +54,13 @@ TERMS_ALL = TERM_DIFFUSION | TERM_EMABS | TERM_NES
 
 BC_ZERO_FLUX = 0
 BC_FREE_STREAM = 1
+BC_GEOMETRIC = 2                 # constant luminosity through a geometric ghost zone (eq. a62af)
+
+LIMITER_NONE = 0
+LIMITER_INTRP = 1
+LIMITER_GEOM = 2                 # min(F_intrp, F_geom), eqs. a20, a23-a26a
+
+R_NU_CM = 3.0e6                  # neutrinosphere radius of a 10 MeV neutrino
 
 # name, rays, zones, groups, species
 CONFIGS = {
@@ -94,6 +104,7 @@ class Workload:
     terms: int = TERMS_ALL
     limiter: int = 1
     psi_floor: float = 1e-300
+    r_nu: Optional[torch.Tensor] = None      # [S][N] neutrinosphere radius R_nu(eps_k) per species, cm
 
     @property
     def n_systems(self) -> int:
@@ -104,9 +115,12 @@ class Workload:
         return self.S * self.R * self.I * self.N
 
     def tensors(self):
-        return dict(r_edge=self.r_edge, e_edge=self.e_edge, temp=self.temp,
-                    kappa_a=self.kappa_a, eta=self.eta, kappa_s=self.kappa_s,
-                    psi_n=self.psi_n, nes_amp=self.nes_amp, nes_g=self.nes_g)
+        t = dict(r_edge=self.r_edge, e_edge=self.e_edge, temp=self.temp,
+                 kappa_a=self.kappa_a, eta=self.eta, kappa_s=self.kappa_s,
+                 psi_n=self.psi_n, nes_amp=self.nes_amp, nes_g=self.nes_g)
+        if self.r_nu is not None:
+            t["r_nu"] = self.r_nu
+        return t
 
     def to(self, device) -> "Workload":
         kw = {k: v.to(device).contiguous() for k, v in self.tensors().items()}
@@ -234,9 +248,10 @@ def _build(name, cfg, S, R_full, I, N, rays, step, spikes, device, c_dt=C_LIGHT 
     nes_amp = (1e-7 * rho / 1e14)[None].expand(S, R, I).contiguous()
     le = torch.log(eps)
     nes_g = torch.exp(-((le[:, None] - le[None, :]) ** 2) / (2.0 * 0.3 ** 2)).contiguous()
+    r_nu = (R_NU_CM * torch.sqrt(eps / 10.0))[None].expand(S, N).contiguous()
     return Workload(name=name, S=S, R=R, I=I, N=N, c_dt=float(c_dt), r_edge=r_edge,
                     e_edge=e_edge.contiguous(), temp=T.contiguous(), kappa_a=kappa_a, eta=eta,
-                    kappa_s=kappa_s, psi_n=psi_n, nes_amp=nes_amp, nes_g=nes_g)
+                    kappa_s=kappa_s, psi_n=psi_n, nes_amp=nes_amp, nes_g=nes_g, r_nu=r_nu)
 
 
 @dataclasses.dataclass
@@ -315,7 +330,6 @@ class EadvInputs:
 
 
 LAPSE_R0_CM = 2.04e5        # the paper's redshift test: a(R) = sqrt(1 - R0/R), R0 = 2.04 km
-R_NU_CM = 3.0e6             # neutrinosphere radius of a 10 MeV neutrino in the Eddington-factor stand-in
 
 
 def eadv_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0,

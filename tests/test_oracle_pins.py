@@ -350,7 +350,8 @@ def test_pins_catch_swapped_nes_kernels(monkeypatch):
 def test_pins_catch_missing_third_in_flux(monkeypatch):
     """Plant a flux without the 1/3 of eq. a59: the quadratic-profile pin must fail."""
     orig = ot.edge_flux
-    monkeypatch.setattr(ot, "edge_flux", lambda u, v, lam, D, fl, lim=1: tuple(3 * x for x in orig(u, v, lam, D, fl, lim)))
+    monkeypatch.setattr(ot, "edge_flux",
+                        lambda u, v, lam, D, fl, lim=1, limb=None: tuple(3 * x for x in orig(u, v, lam, D, fl, lim, limb)))
     with pytest.raises(AssertionError):
         test_diffusion_operator_on_quadratic_profile()
 

@@ -78,9 +78,22 @@ typedef enum {
 
 #define TM_BC_ZERO_FLUX   0   /* psi^(1) = 0 at the boundary (inner: the paper's centre condition) */
 #define TM_BC_FREE_STREAM 1   /* outer only: psi^(1) = psi^(0) of the last zone (limit eq. a22)     */
+#define TM_BC_GEOMETRIC   2   /* outer only: constant luminosity through a ghost zone (eq. a62af, with
+                                 R_nu squared): the ghost centre R_{I+1} = 2 R_{I+1/2} - R_I mirrors the
+                                 last zone's centre across the outer edge and holds
+                                 psi_{I+1} = psi_I (R_I^2 - R_nu^2/4) / (R_{I+1}^2 - R_nu^2/4), the ratio
+                                 clipped to [0, 1]; the outer flux is the limited edge flux of eq. a59
+                                 between zone I and the ghost, with the last zone's mean free path.
+                                 Needs tm_inputs.r_nu.                                                */
 
 #define TM_LIMITER_NONE   0   /* F = 1 (pure diffusion, eq. a21)                       */
 #define TM_LIMITER_INTRP  1   /* F = F_intrp of eq. a20                                */
+#define TM_LIMITER_GEOM   2   /* F = min(F_intrp, F_geom) (eqs. a23-a26a): at an edge of radius R
+                                 outside the neutrinosphere of the group, F_geom = (1 + mu_nu) m / 2
+                                 over lam |psi_{i+1} - psi_i| / (3 D), mu_nu = sqrt(1 - (R_nu/R)^2)
+                                 (no matter velocity, no ray bending), m the floored edge mean; 1
+                                 inside.  Where F_geom is the smaller, H = (1 + mu_nu) m / 2 times
+                                 -sign(psi_{i+1} - psi_i) (eq. a26b).  Needs tm_inputs.r_nu.       */
 
 #define TM_PREC_FP64  0       /* everything in float64                                 */
 #define TM_PREC_MIXED 1       /* block factorisation and solve in float32; residual,
@@ -104,7 +117,7 @@ typedef struct {
     int32_t  n_groups;    /* N, 1 <= N <= TM_MAX_GROUPS                                */
     double   c_dt;        /* c * dt in cm (> 0)                                        */
     int32_t  inner_bc;    /* must be TM_BC_ZERO_FLUX                                   */
-    int32_t  outer_bc;    /* TM_BC_ZERO_FLUX or TM_BC_FREE_STREAM                      */
+    int32_t  outer_bc;    /* TM_BC_ZERO_FLUX, TM_BC_FREE_STREAM or TM_BC_GEOMETRIC     */
     uint32_t terms;       /* TM_TERM_* bitmask                                         */
     int32_t  limiter;     /* TM_LIMITER_*                                              */
     double   psi_floor;   /* floor of the edge mean in the limiter (> 0), e.g. 1e-300  */
@@ -122,6 +135,8 @@ typedef struct {
     const double *nes_g;    /* [N][N] symmetric shape; may be NULL when TM_TERM_NES is off */
     const double *lapse;    /* zone [R][I], lapse a_i at zone centres (> 0); NULL: a = 1       */
     const double *lapse_edge; /* edge [R][I+1], lapse at zone edges; given with lapse or not at all */
+    const double *r_nu;     /* [S][N] cm, neutrinosphere radius R_nu of each species and group;
+                               required by TM_LIMITER_GEOM and TM_BC_GEOMETRIC, else may be NULL */
 } tm_inputs;
 
 /* The lapse (eq. a58 with a != 1; eq. a8a).  With `lapse` set, the residual is a_i c dt times eq. a58:
@@ -243,7 +258,9 @@ tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
  * written as a cell array: seed = dL_N/dpsi + add, where dL_N/dpsi = c R_{I+1/2}^2 W_k in
  * the outermost zone and zero elsewhere (zero everywhere without an outgoing flux).
  * `add` (cell array) may be NULL or alias `seed`; a multi-step adjoint passes the adjoint of
- * the following step there.  Needs r_edge and e_edge only.                          */
+ * the following step there.  Needs r_edge and e_edge only.  With TM_BC_GEOMETRIC the outer
+ * flux depends on psi_I through the limited flux to the ghost zone, so its derivative needs
+ * the state: this entry point then returns TM_ERR_INVALID_ARG.                        */
 tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, const double *add, double *seed);
 
 /* ---------------------------------------------------------------------------------

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_factor_q.hip", "tm_ye.hip", "tm_energy.hip"]
+SOURCES = ["tm_api.hip", "tm_residual.hip", "tm_factor.hip", "tm_factor_geo.hip", "tm_factor_q.hip", "tm_ye.hip",
+           "tm_energy.hip"]
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")
 
 

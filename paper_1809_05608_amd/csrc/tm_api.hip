@@ -86,9 +86,11 @@ bool valid_problem(const tm_problem* p, std::string* why) {
     if (p->n_groups < 1 || p->n_groups > TM_MAX_GROUPS) return fail("N must be in [1, 32]");
     if (!(p->c_dt > 0.0) || !std::isfinite(p->c_dt)) return fail("c_dt must be finite and > 0");
     if (p->inner_bc != TM_BC_ZERO_FLUX) return fail("inner_bc must be TM_BC_ZERO_FLUX");
-    if (p->outer_bc != TM_BC_ZERO_FLUX && p->outer_bc != TM_BC_FREE_STREAM) return fail("bad outer_bc");
+    if (p->outer_bc != TM_BC_ZERO_FLUX && p->outer_bc != TM_BC_FREE_STREAM && p->outer_bc != TM_BC_GEOMETRIC)
+        return fail("bad outer_bc");
     if (p->terms & ~TM_TERMS_ALL) return fail("unknown bit in terms");
-    if (p->limiter != TM_LIMITER_NONE && p->limiter != TM_LIMITER_INTRP) return fail("bad limiter");
+    if (p->limiter != TM_LIMITER_NONE && p->limiter != TM_LIMITER_INTRP && p->limiter != TM_LIMITER_GEOM)
+        return fail("bad limiter");
     if (!(p->psi_floor > 0.0)) return fail("psi_floor must be > 0");
     if (p->precision != TM_PREC_FP64 && p->precision != TM_PREC_MIXED) return fail("bad precision");
     if (n_systems(*p) > 0x7fffffffLL) return fail("too many systems");
@@ -119,6 +121,7 @@ tmk::Fields fields_of(const tm_inputs& in) {
     f.nes_amp = in.nes_amp;
     f.lapse = in.lapse;
     f.lapse_edge = in.lapse_edge;
+    f.r_nu = in.r_nu;
     return f;
 }
 
@@ -146,6 +149,8 @@ tm_status check_inputs(tm_ctx* c, const tm_inputs* in, bool need_opacity = true)
     if ((c->p.terms & TM_TERM_NES) && (!in->nes_amp || !in->nes_g || !in->temp))
         return set_err(c, TM_ERR_INVALID_ARG, "nes_amp, nes_g and temp are required when TM_TERM_NES is on");
     if (!in->lapse != !in->lapse_edge) return set_err(c, TM_ERR_INVALID_ARG, "lapse and lapse_edge go together");
+    if ((c->p.limiter == TM_LIMITER_GEOM || c->p.outer_bc == TM_BC_GEOMETRIC) && !in->r_nu)
+        return set_err(c, TM_ERR_INVALID_ARG, "r_nu is required by TM_LIMITER_GEOM and TM_BC_GEOMETRIC");
     return TM_OK;
 }
 
@@ -975,6 +980,9 @@ tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, 
     if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
     if (!seed) return set_err(c, TM_ERR_INVALID_ARG, "seed is required");
     TM_TRY(no_lapse(c, in, "the luminosity seed (the adjoint path)"));
+    if (c->p.outer_bc == TM_BC_GEOMETRIC)
+        return set_err(c, TM_ERR_INVALID_ARG,
+                       "the luminosity seed of TM_BC_GEOMETRIC depends on psi (this entry point takes none)");
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));

@@ -29,9 +29,9 @@ struct Consts {
 struct Shape {
     int S, R, I, N;
     double c_dt;
-    int outer_bc;      // 0 zero flux, 1 free streaming
+    int outer_bc;      // 0 zero flux, 1 free streaming, 2 geometric ghost zone (eq. a62af)
     unsigned terms;    // TM_TERM_* bits
-    int limiter;       // 0 none, 1 F_intrp
+    int limiter;       // 0 none, 1 F_intrp, 2 min(F_intrp, F_geom)
     double psi_floor;
 };
 
@@ -45,6 +45,7 @@ struct Fields {
     const double* nes_amp;  // [S][R][I]
     const double* lapse;        // [R][I] lapse at zone centres, or nullptr (a = 1)
     const double* lapse_edge;   // [R][I+1] lapse at zone edges (set together with lapse)
+    const double* r_nu;         // [S][N] neutrinosphere radius per species and group (limiter 2, outer_bc 2)
 };
 
 // Lapse factors of eq. a58 times a_i c dt: the flux difference of zone i carries a_i^3 / V_i and the
@@ -84,8 +85,35 @@ __device__ __forceinline__ double drcp(double x) {
     return fma(r, e, r);
 }
 
+// (1 + mu_nu)/2 of the geometric limiter at radius R for a neutrinosphere of radius rnu (eqs. a24-a26
+// with beta = 0 and no ray bending, mu_nu = sqrt(1 - (R_nu/R)^2)); -1 inside the neutrinosphere, where
+// there is no geometric limit (F_geom = 1).
+__device__ __forceinline__ double limb_factor(double R, double rnu) {
+    if (!(R > rnu)) return -1.0;
+    const double x = rnu / R;
+    return 0.5 * (1.0 + sqrt(1.0 - x * x));
+}
+
+// Ghost zone of the geometric outer boundary (eq. a62af, R_nu squared) for a last zone with edges rlo,
+// rhi: centre R_{I+1} at the mirror of R_I across the outer edge, psi_{I+1} = ratio psi_I with
+// ratio = (R_I^2 - R_nu^2/4) / (R_{I+1}^2 - R_nu^2/4) clipped to [0, 1], and the outer edge's D.
+struct Ghost {
+    double ratio, D;
+};
+__device__ __forceinline__ Ghost outer_ghost(double rlo, double rhi, double rnu) {
+    const double RI = 0.5 * (rlo + rhi), Rg = 2.0 * rhi - RI, q = 0.25 * rnu * rnu;
+    const double den = Rg * Rg - q;
+    Ghost g;
+    g.ratio = den > 0.0 ? fmin(fmax((RI * RI - q) / den, 0.0), 1.0) : 0.0;
+    g.D = Rg - RI;
+    return g;
+}
+
+// With limiter 2 and limb = (1 + mu_nu)/2 > 0 (outside the neutrinosphere), F = min(F_intrp, F_geom)
+// (eq. a26a), F_geom = limb m / (lam |v - u| / (3 D)) (eq. a23): where it is the smaller factor
+// (limb (3 D m + lam |v - u|) < lam |v - u|) the flux is H = -limb m sign(v - u) (eq. a26b).
 __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, double D,
-                                              double floor, int limiter) {
+                                              double floor, int limiter, double limb = -1.0) {
     EdgeFlux f;
     const double delta = v - u;
     if (limiter == 0) {
@@ -100,6 +128,15 @@ __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, do
     const double m = fmax(mean, floor);
     const double ad = fabs(delta);
     const double den = fma(3.0 * D, m, lam * ad);
+    if (limiter == 2 && limb > 0.0 && ad > 0.0 && limb * den < lam * ad) {
+        const double sg = delta > 0.0 ? 1.0 : -1.0;
+        f.H = -limb * m * sg;
+        const double d = (mean > floor) ? -0.5 * limb * sg : 0.0;
+        f.dHu = d;
+        f.dHv = d;
+        f.dHlam = 0.0;
+        return f;
+    }
     const double inv = drcp(den);
     const double r = m * inv;             // m / den
     const double q = delta * inv;         // delta / den

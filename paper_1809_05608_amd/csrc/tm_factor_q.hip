@@ -65,8 +65,10 @@ __device__ __forceinline__ double drcp1(double x) {
 struct FluxD {
     float dHu, dHv;
 };
+// With limiter 2 and limb = (1 + mu_nu)/2 > 0 the geometric piece is taken where it is the smaller factor,
+// limb (3 D + lam |rho|) < lam |rho|; there H = -limb m sign(v - u) and dH/du = dH/dv = -limb sign / 2.
 __device__ __forceinline__ FluxD flux_derivatives(double u, double v, float lam, float D3, double floor,
-                                                  int limiter) {
+                                                  int limiter, float limb = -1.0f) {
     FluxD f;
     if (limiter == 0) {
         const float gl = lam / D3;
@@ -84,7 +86,19 @@ __device__ __forceinline__ FluxD flux_derivatives(double u, double v, float lam,
     const float dHm = (mean > floor) ? -lam * lam * w * fabsf(w) : 0.0f;
     f.dHu = 0.5f * dHm - dHd;
     f.dHv = 0.5f * dHm + dHd;
+    if (limiter == 2 && limb > 0.0f && rho != 0.0f && limb * fmaf(lam, fabsf(rho), D3) < lam * fabsf(rho)) {
+        const float d = (mean > floor) ? (rho > 0.0f ? -0.5f * limb : 0.5f * limb) : 0.0f;
+        f.dHu = d;
+        f.dHv = d;
+    }
     return f;
+}
+
+// (1 + mu_nu)/2 at radius R outside a neutrinosphere of radius rnu (eqs. a24-a26, beta = 0, no ray
+// bending), -1 inside it; float32, for the Jacobian.
+__device__ __forceinline__ float limb_f(double R, float rnu) {
+    const float x = rnu / (float)R;
+    return x < 1.0f ? 0.5f * (1.0f + sqrtf(fmaf(-x, x, 1.0f))) : -1.0f;
 }
 
 // Scheduling fence: keeps the fully unrolled sweeps from hoisting the loads and broadcasts of later
@@ -227,6 +241,15 @@ void k_factor_q(FactorArgs A) {
         }
         s_rs[0][lane] = rs_in;
         s_rs[1][lane] = rs_out;
+    }
+    // neutrinosphere radius of the lane's rows, for the geometric limiter and the geometric outer boundary
+    __shared__ float s_rnu[R][kQuadBlock];
+    if (sh.limiter == 2 || sh.outer_bc == 2) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int k = 4 * s + (lane & 3);
+            s_rnu[s][lane] = k < N ? (float)A.f.r_nu[(size_t)(sys / sh.R) * N + k] : 0.0f;
+        }
     }
 
 
@@ -443,7 +466,8 @@ void k_factor_q(FactorArgs A) {
                 const float lam_n = frcp((float)(ah.ka[s] + ah.et[s] + ah.ks[s]));
                 if (diff) {
                     const FluxD e = flux_derivatives(psi_c, psi_n, sqrtf(s_clam[s][lane] * lam_n), D3,
-                                                     sh.psi_floor, sh.limiter);
+                                                     sh.psi_floor, sh.limiter,
+                                                     sh.limiter == 2 ? limb_f(r1, s_rnu[s][lane]) : -1.0f);
                     dHu_hi = real ? e.dHu : 0.0f;
                     dHv_hi = real ? e.dHv : 0.0f;
                 }
@@ -453,6 +477,16 @@ void k_factor_q(FactorArgs A) {
                 s_clam[s][lane] = lam_n;
             } else if (sh.outer_bc == 1) {
                 dHu_hi = 1.0f;         // free streaming: H = psi of the last zone
+            } else if (sh.outer_bc == 2 && diff) {
+                // ghost zone of eq. a62af (R_nu squared): psi_{I+1} = ratio psi_I at the mirror centre
+                const double rnu = s_rnu[s][lane];
+                const double RI = 0.5 * (r0 + r1), Rg = 2.0 * r1 - RI, qn = 0.25 * rnu * rnu;
+                const double den = Rg * Rg - qn;
+                const double ratio = den > 0.0 ? fmin(fmax((RI * RI - qn) / den, 0.0), 1.0) : 0.0;
+                const FluxD e = flux_derivatives(psi_c, ratio * psi_c, s_clam[s][lane], (float)(3.0 * (Rg - RI)),
+                                                 sh.psi_floor, sh.limiter,
+                                                 sh.limiter == 2 ? limb_f(r1, (float)rnu) : -1.0f);
+                dHu_hi = real ? e.dHu + (float)ratio * e.dHv : 0.0f;
             }
             float diag = 1.0f, bm = 0.0f, bp = 0.0f;
             if (diff) {

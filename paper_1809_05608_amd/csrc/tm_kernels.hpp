@@ -93,6 +93,7 @@ enum FactorKernel : int {
 hipError_t launch_factor(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st,
                          int kernel = kFactorQuadMfma);
 bool launch_factor_quad(const FactorArgs& a, hipStream_t st, int kernel);
+hipError_t launch_factor_geo(const FactorArgs& a, bool fp32, bool transpose, bool pivot, hipStream_t st);
 
 hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const double* psi,
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,

@@ -184,6 +184,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     double s_n = 0.0, s_nold = 0.0, s_e = 0.0, s_q = 0.0, s_nes = 0.0, s_b = 0.0;
     const double Wk = lane_ok ? cs->W[k] : 0.0;
     const double epsk = lane_ok ? cs->eps[k] : 0.0;
+    const bool geo = sh.limiter == 2 || sh.outer_bc == 2;       // neutrinosphere radii in use
+    const double rnuk = (geo && lane_ok) ? f.r_nu[(size_t)(sys / sh.R) * N + k] : 0.0;
     const double dek = (lane_ok && k + 1 < N) ? cs->de[k] : 0.0;
     const size_t sys_cell0 = (size_t)sys * I * N;
 
@@ -253,13 +255,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
                         const double rlo = s_re[zl], rhi = s_re[zl + 1], rp = s_re[zl + 2];
                         const double D = 0.5 * (rhi + rp) - 0.5 * (rlo + rhi);
                         const EdgeFlux e = edge_flux(p, s_psi[zl + 1][k], sqrt(lam * s_lam[zl + 1][k]), D,
-                                                     sh.psi_floor, sh.limiter);
+                                                     sh.psi_floor, sh.limiter,
+                                                     sh.limiter == 2 ? limb_factor(rhi, rnuk) : -1.0);
                         H = e.H;
                         du = e.dHu;
                         dv = e.dHv;
                     } else if (sh.outer_bc == 1) {
                         H = p;                              // free streaming, eq. a22 limit
                         du = 1.0;
+                    } else if (sh.outer_bc == 2) {          // ghost zone of eq. a62af
+                        const double rlo = s_re[zl], rhi = s_re[zl + 1];
+                        const Ghost gh = outer_ghost(rlo, rhi, rnuk);
+                        const EdgeFlux e = edge_flux(p, gh.ratio * p, lam, gh.D, sh.psi_floor, sh.limiter,
+                                                     sh.limiter == 2 ? limb_factor(rhi, rnuk) : -1.0);
+                        H = e.H;
+                        du = e.dHu + gh.ratio * e.dHv;
                     }
                 }
                 s_H[zl][k] = H;                             // the edge below zone 0 has zero flux
@@ -437,22 +447,29 @@ __global__ __launch_bounds__(kBlock) void k_blocks(Shape sh, Fields f, const Con
             double diag = 1.0, bm = 0.0, bp = 0.0;
             if (sh.terms & kDiffusion) {
                 const double lam = inv_mfp(f, cb + k);
+                const double rnu = (sh.limiter == 2 || sh.outer_bc == 2) ? f.r_nu[(size_t)(sys / sh.R) * N + k] : 0.0;
+                auto limb = [&](double R) { return sh.limiter == 2 ? limb_factor(R, rnu) : -1.0; };
                 double dHv_lo = 0.0, dHu_lo = 0.0, dHu_hi = 0.0, dHv_hi = 0.0;
                 if (i > 0) {
                     const size_t cm = cb - N + k;
                     const EdgeFlux e = edge_flux(psi[cm], p[k], sqrt(lam * inv_mfp(f, cm)), g.D_lo,
-                                                 sh.psi_floor, sh.limiter);
+                                                 sh.psi_floor, sh.limiter, limb(re[i]));
                     dHu_lo = e.dHu;
                     dHv_lo = e.dHv;
                 }
                 if (i + 1 < I) {
                     const size_t cp = cb + N + k;
                     const EdgeFlux e = edge_flux(p[k], psi[cp], sqrt(lam * inv_mfp(f, cp)), g.D_hi,
-                                                 sh.psi_floor, sh.limiter);
+                                                 sh.psi_floor, sh.limiter, limb(re[i + 1]));
                     dHu_hi = e.dHu;
                     dHv_hi = e.dHv;
                 } else if (sh.outer_bc == 1) {
                     dHu_hi = 1.0;
+                } else if (sh.outer_bc == 2) {
+                    const Ghost gh = outer_ghost(re[i], re[i + 1], rnu);
+                    const EdgeFlux e = edge_flux(p[k], gh.ratio * p[k], lam, gh.D, sh.psi_floor, sh.limiter,
+                                                 limb(re[i + 1]));
+                    dHu_hi = e.dHu + gh.ratio * e.dHv;
                 }
                 diag += c * (g.A_hi * dHu_hi - g.A_lo * dHv_lo) / g.V;
                 bp = (i + 1 < I) ? c * g.A_hi * dHv_hi / g.V : 0.0;
@@ -520,17 +537,24 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
             const double lam = inv_mfp(f, cb);
             double gchi = 0.0;     // sum over the two edges of (mu-weighted dG/dH) dH/dlam dlam/dchi
             if (diff) {
+                const double rnu = (sh.limiter == 2 || sh.outer_bc == 2) ? f.r_nu[(size_t)(sys / sh.R) * N + k] : 0.0;
+                auto limb = [&](double R) { return sh.limiter == 2 ? limb_factor(R, rnu) : -1.0; };
                 if (i + 1 < I) {
                     const size_t cp = cb + N;
                     const double lam_e = sqrt(lam * inv_mfp(f, cp));
-                    const EdgeFlux e = edge_flux(pk, psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter);
+                    const EdgeFlux e = edge_flux(pk, psi[cp], lam_e, g.D_hi, sh.psi_floor, sh.limiter, limb(re[i + 1]));
                     const double w = c * g.A_hi * (m0 / g.V - mu[cp] / g.V_hi);
                     gchi += w * e.dHlam * (-0.5 * lam_e * lam);
+                } else if (sh.outer_bc == 2) {
+                    // the ghost-zone flux carries the last zone's own mean free path: dlam/dchi = -lam^2
+                    const Ghost gh = outer_ghost(re[i], re[i + 1], rnu);
+                    const EdgeFlux e = edge_flux(pk, gh.ratio * pk, lam, gh.D, sh.psi_floor, sh.limiter, limb(re[i + 1]));
+                    gchi += c * g.A_hi * (m0 / g.V) * e.dHlam * (-lam * lam);
                 }
                 if (i > 0) {
                     const size_t cm = cb - N;
                     const double lam_e = sqrt(lam * inv_mfp(f, cm));
-                    const EdgeFlux e = edge_flux(psi[cm], pk, lam_e, g.D_lo, sh.psi_floor, sh.limiter);
+                    const EdgeFlux e = edge_flux(psi[cm], pk, lam_e, g.D_lo, sh.psi_floor, sh.limiter, limb(re[i]));
                     const double w = c * g.A_lo * (mu[cm] / g.V_lo - m0 / g.V);
                     gchi += w * e.dHlam * (-0.5 * lam_e * lam);
                 }

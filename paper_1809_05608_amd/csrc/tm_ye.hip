@@ -171,7 +171,9 @@ __device__ __forceinline__ double lane_value(double v, int p) {
 template <int NT>
 constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
 
-template <int NT, int WEU>
+// GEO: the geometric limiter and outer boundary compiled in (instantiated separately, at one wave per SIMD,
+// and launched only for problems that ask for either).
+template <int NT, int WEU, bool GEO>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) void k_ye_factor(YeFactorArgs A) {
     constexpr int MT = 2 * NT + 1;              // rows of a coupled block (<= 57)
     constexpr int NC = 2 * NT;                  // columns of C that can be non-zero (Y_e has bp = 0)
@@ -264,12 +266,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         if (i + 1 < I) {
             const double D_hi = 0.5 * (rhi + re[i + 2]) - 0.5 * (rlo + rhi);
             if (diff && real) {
-                const EdgeFlux e = edge_flux(psi_c, psi_n1, sqrt(lam_c * lam_n1), D_hi, sh.psi_floor, sh.limiter);
+                const double limb = (GEO && sh.limiter == 2) ? limb_factor(rhi, A.f.r_nu[(size_t)q * N + kk]) : -1.0;
+                const EdgeFlux e = edge_flux(psi_c, psi_n1, sqrt(lam_c * lam_n1), D_hi, sh.psi_floor, sh.limiter, limb);
                 dHu_hi = e.dHu;
                 dHv_hi = e.dHv;
             }
         } else if (sh.outer_bc == 1) {
             dHu_hi = 1.0;                                   // free streaming: H = psi of the last zone
+        } else if (GEO && sh.outer_bc == 2 && diff && real) {     // ghost zone of eq. a62af
+            const double rnu = A.f.r_nu[(size_t)q * N + kk];
+            const Ghost gh = outer_ghost(rlo, rhi, rnu);
+            const EdgeFlux e = edge_flux(psi_c, gh.ratio * psi_c, lam_c, gh.D, sh.psi_floor, sh.limiter,
+                                         sh.limiter == 2 ? limb_factor(rhi, rnu) : -1.0);
+            dHu_hi = e.dHu + gh.ratio * e.dHv;
         }
         double diag = 1.0, bm = 0.0, bp = 0.0;
         if (diff) {
@@ -610,7 +619,11 @@ hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
     TM_YE_DISPATCH(padded_groups(a.sh.N),
                    constexpr int WPB = ye_waves_per_block<NT>();
                    const long long blocks = (a.nray + WPB - 1) / WPB;
-                   hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>()>), dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a))
+                   if (a.sh.limiter == 2 || a.sh.outer_bc == 2)
+                       hipLaunchKernelGGL((k_ye_factor<NT, 1, true>), dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a);
+                   else
+                       hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>(), false>), dim3((unsigned)blocks),
+                                          dim3(64 * WPB), 0, st, a))
     return hipGetLastError();
 }
 

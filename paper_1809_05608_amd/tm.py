@@ -47,7 +47,8 @@ class Problem(ctypes.Structure):
 
 class Inputs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
-                ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp", "nes_amp", "nes_g", "lapse", "lapse_edge")]
+                ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp", "nes_amp", "nes_g", "lapse", "lapse_edge",
+                 "r_nu")]
 
 
 class Stats(ctypes.Structure):
@@ -138,11 +139,13 @@ class DeviceFields:
     nes_g: torch.Tensor
     lapse: Optional[torch.Tensor] = None        # [R][I] lapse at zone centres (None: a = 1)
     lapse_edge: Optional[torch.Tensor] = None   # [R][I+1] lapse at zone edges
+    r_nu: Optional[torch.Tensor] = None         # [S][N] neutrinosphere radii (geometric limiter / boundary)
 
     @classmethod
     def of(cls, w, **override):
         d = {k: getattr(w, k) for k in ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp",
                                          "nes_amp", "nes_g")}
+        d["r_nu"] = getattr(w, "r_nu", None)
         d.update(override)
         return cls(**d)
 
@@ -204,6 +207,8 @@ class Context:
             raise ValueError("lapse and lapse_edge go together")
         if f.lapse is not None:
             exp.update(lapse=(p.n_rays, p.n_zones), lapse_edge=(p.n_rays, p.n_zones + 1))
+        if f.r_nu is not None:
+            exp.update(r_nu=(p.n_species, p.n_groups))
         for name, shape in exp.items():
             t = getattr(f, name)
             if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous():
@@ -212,7 +217,7 @@ class Context:
                 raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
         self._keep = f
         return Inputs(*[_ptr(getattr(f, n)) for n in ("r_edge", "e_edge", "kappa_a", "eta", "kappa_s", "temp",
-                                                       "nes_amp", "nes_g", "lapse", "lapse_edge")])
+                                                       "nes_amp", "nes_g", "lapse", "lapse_edge", "r_nu")])
 
     def set_workspace(self, nbytes: int):
         """Give the context a caller-owned workspace of `nbytes` (a torch uint8 tensor)."""

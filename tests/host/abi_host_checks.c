@@ -55,7 +55,7 @@ int main(void) {
     bad[6].c_dt = -1.0;
     bad[7].outer_bc = 7;
     bad[8].terms = 8u;
-    bad[9].limiter = 2;
+    bad[9].limiter = 3;
     bad[10].psi_floor = 0.0;
     bad[11].precision = 3;
     for (int j = 0; j < 12; ++j) {

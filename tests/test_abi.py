@@ -67,7 +67,7 @@ def _prob(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(N=33), dict(I=0), dict(R=0), dict(S=0), dict(c_dt=0.0),
-                                 dict(c_dt=float("nan")), dict(outer_bc=7), dict(terms=8), dict(limiter=2),
+                                 dict(c_dt=float("nan")), dict(outer_bc=7), dict(outer_bc=3), dict(terms=8), dict(limiter=3),
                                  dict(psi_floor=0.0), dict(precision=3)])
 def test_invalid_problem_rejected_before_device_work(bad):
     lib = tm.load_library()

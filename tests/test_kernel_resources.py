@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BUILD = os.path.join(ROOT, "_build")
 LLVM = "/opt/rocm/llvm/bin"
-SOURCES = ["tm_residual", "tm_factor", "tm_factor_q", "tm_ye", "tm_energy"]
+SOURCES = ["tm_residual", "tm_factor", "tm_factor_geo", "tm_factor_q", "tm_ye", "tm_energy"]
 
 # kernels that may use scratch: the debug Jacobian output and the per-zone temperature update, neither
 # on a timed path

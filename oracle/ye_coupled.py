@@ -11,7 +11,10 @@ and "Solution of the Transport Equations"):
 * eq. a62ae: the combined block-tridiagonal system of N_nu x N_k + 1 unknowns per zone, here
   the two coupled species, so 2N + 1 (psi of nu_e, psi of anti-nu_e, Y_e);
 * eqs. a62b, a62d: the internal-energy change of the matter and the temperature update computed
-  after the implicit solve.
+  after the implicit solve;
+* eqs. d11-d22 (optional): neutrino-antineutrino pair creation and annihilation coupling the two
+  species of the block, with the angular cutoff factor chi = min(chi_1, chi_2) on the annihilation
+  kernel.
 
 Only `tests/` may import this module.  It shares no code with the HIP path.
 
@@ -28,7 +31,21 @@ Readings (the paper is silent or garbled here):
         T^{n+1} = T^n + (e^{n+1} - e^n - (Y_e^{n+1} - Y_e^n) (de/dY_e)_{rho,T}) / (de/dT)_{rho,Y_e}
     (the printed "+" and the subscript "rho, Y_e" on de/dY_e are read as a garble of a first-order
     expansion of e(T, Y_e) at fixed rho);
-  * energies of eq. a62b are in MeV per baryon; e and its derivatives are inputs in those units.
+  * energies of eq. a62b are in MeV per baryon; e and its derivatives are inputs in those units;
+  * pair processes enter moment 0 through the Phi_0 terms of eq. d14 (the Phi_1 terms, products of the
+    two species' first moments, are dropped as for the NES kernel); in the discrete form the sums over
+    eps' carry the weights W_k' (eq. a01b), the annihilation kernel is Q^a_{kk'} = a_i g_{kk'} W_k'/Wbar
+    with a symmetric shape g (so that W_k Q^a_{kk'} is symmetric and pairs conserve nu - anti-nu
+    number), and the creation kernel is Q^p = exp(-(eps_k + eps_k')/T) Q^a (eq. d12: the electron and
+    positron carry the pair's energy);
+  * chi_1 (eq. d16) takes the zone-centred flux factors psi1/psi0 of both species as inputs, so it does
+    not depend on the unknowns; its printed closed form, 1 - (1/6) eta eta', does not follow from the
+    ratio of angular integrals that eq. d16 states as its definition, which evaluates to
+    1 - (3/2) eta eta' for f = psi0 + 3 mu psi1; the definition is taken; chi_2 (eq. d19) uses R = the zone centre and the cosines of eq. d22,
+    whose "sign" is Fortran's SIGN(a, b) (|a| with the sign of b): mu = sqrt(1 - x^2) for x = R_nu/R <= 1
+    and -sqrt(x^2 - 1) clipped at -1 inside the neutrinosphere;
+  * the pair sources join the collision energy of the temperature update (the pair's energy comes from
+    the matter's electrons and positrons).
 
 Parity status: pinned by `tests/test_oracle_ye.py` (total lepton-number conservation, total
 energy conservation through the temperature update, the decoupled limit against the
@@ -60,6 +77,9 @@ class CoupledSystem:
     ye_n: np.ndarray            # [I] Y_e at step n
     dka_dye: np.ndarray         # [2][I][N] dkappa_a/dY_e of nu_e, anti-nu_e (cm^-1)
     deta_dye: np.ndarray        # [2][I][N] deta/dY_e (cm^-1)
+    pair_amp: Optional[np.ndarray] = None    # [I] cm^-1, pair-kernel amplitude (None: no pair processes)
+    pair_g: Optional[np.ndarray] = None      # [N][N] symmetric shape of the pair kernels
+    pair_eta1: Optional[np.ndarray] = None   # [2][I][N] flux factors psi1/psi0 of nu_e and anti-nu_e
 
     @property
     def I(self) -> int:
@@ -77,9 +97,71 @@ class CoupledSystem:
 def coupled_systems(w: dict, ye: dict) -> list:
     """CoupledSystem of every ray from workload arrays (`Workload.numpy()`) and `YeInputs.numpy()`."""
     sy = tr.systems_from_workload(w)
+    pairs = ye.get("pair_amp") is not None
     return [CoupledSystem(nue=sy[0][r], nuebar=sy[1][r], rho=ye["rho"][r], ye_n=ye["ye_n"][r],
-                          dka_dye=ye["dka_dye"][:, r], deta_dye=ye["deta_dye"][:, r])
+                          dka_dye=ye["dka_dye"][:, r], deta_dye=ye["deta_dye"][:, r],
+                          pair_amp=ye["pair_amp"][r] if pairs else None, pair_g=ye["pair_g"] if pairs else None,
+                          pair_eta1=ye["pair_eta1"][:, r] if pairs else None)
             for r in range(w["R"])]
+
+
+# ---------------------------------------------------------------- pair processes (eqs. d11-d22)
+
+def limb_cosine(x):
+    """Cosine of eq. d22 for x = R_nu/R: sqrt(1 - x^2) outside the neutrinosphere (eq. d17), and
+    -sqrt(x^2 - 1) clipped at -1 inside it."""
+    x = np.asarray(x, dtype=np.float64)
+    v = 1.0 - x * x
+    return np.maximum(np.copysign(np.sqrt(np.abs(v)), v), -1.0)
+
+
+def chi1(eta1_nu, eta1_nubar):
+    """Angular factor of the annihilation rate for nearly isotropic distributions: the ratio that defines
+    eq. d16, evaluated for f = psi0 + 3 mu psi1 (eq. d15), is 1 - (3/2)(psi1/psi0)(psi1bar/psi0bar)
+    (the averages of (1 - n.n')^2 are 4/3 isotropic and -2 psi1 psi1bar from the dipoles)."""
+    return 1.0 - 1.5 * np.asarray(eta1_nu) * np.asarray(eta1_nubar)
+
+
+def chi2(mu, mubar):
+    """Angular factor for radiation beamed from the neutrinospheres (eq. d19)."""
+    mu, mubar = np.asarray(mu), np.asarray(mubar)
+    return (8.0 + (mu * mubar - 3.0) * (1.0 + mu) * (1.0 + mubar)) / 8.0
+
+
+def pair_chi(cs: CoupledSystem) -> np.ndarray:
+    """chi_{i,k,k'} = min(chi_1, chi_2) (eq. d21) for a nu_e of group k and an anti-nu_e of group k' in
+    zone i: [I][N][N]."""
+    Rc = geometry(cs.nue.r_edge)[0]
+    mu = limb_cosine(cs.nue.r_nu[None, :] / Rc[:, None])            # [I][N]
+    mub = limb_cosine(cs.nuebar.r_nu[None, :] / Rc[:, None])
+    c1 = chi1(cs.pair_eta1[0][:, :, None], cs.pair_eta1[1][:, None, :])
+    c2 = chi2(mu[:, :, None], mub[:, None, :])
+    return np.minimum(c1, c2)
+
+
+def pair_kernels(cs: CoupledSystem):
+    """Annihilation and creation kernels [I][N][N] seen from the nu_e (row k, anti-nu_e group k') and from
+    the anti-nu_e (row k', nu_e group k): Q^a_{kk'} = a g_{kk'} W_k'/Wbar, Qbar^a_{k'k} = a g_{kk'} W_k/Wbar,
+    and the creation kernels times exp(-(eps_k + eps_k')/T) (eq. d12)."""
+    eps, W = group_energies(cs.nue.e_edge)
+    Wbar = W.mean()
+    base = cs.pair_amp[:, None, None] * cs.pair_g[None, :, :]
+    qa = base * (W / Wbar)[None, None, :]
+    qba = np.transpose(base, (0, 2, 1)) * (W / Wbar)[None, None, :]
+    boltz = np.exp(-(eps[:, None] + eps[None, :])[None] / cs.nue.temp[:, None, None])
+    return qa, boltz * qa, qba, np.transpose(boltz, (0, 2, 1)) * qba
+
+
+def pair_sources(cs: CoupledSystem, pe: np.ndarray, pa: np.ndarray):
+    """Zeroth-moment pair sources of both species (eq. d14, Phi_0 terms), [I][N] each:
+        S_nu,k = (1 - psi_k) sum_k' Q^p_{kk'} (1 - psibar_k') - psi_k sum_k' Q^a_{kk'} chi_{kk'} psibar_k'
+    and the same with the roles of the species exchanged."""
+    qa, qp, qba, qbp = pair_kernels(cs)
+    chi = pair_chi(cs)
+    chib = np.transpose(chi, (0, 2, 1))
+    s_e = (1.0 - pe) * np.einsum("ikl,il->ik", qp, 1.0 - pa) - pe * np.einsum("ikl,il->ik", qa * chi, pa)
+    s_a = (1.0 - pa) * np.einsum("ikl,il->ik", qbp, 1.0 - pe) - pa * np.einsum("ikl,il->ik", qba * chib, pe)
+    return s_e, s_a
 
 
 def zeta(cs: CoupledSystem) -> np.ndarray:
@@ -120,6 +202,10 @@ def residual(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> np.ndarray:
             # the Y_e-dependent part of -eta (1 - psi) + kappa_a psi
             G = G + c * dy[:, None] * (cs.dka_dye[q] * p - cs.deta_dye[q] * (1.0 - p))
         out[:, q * N:(q + 1) * N] = G
+    if cs.pair_amp is not None:
+        s_e, s_a = pair_sources(cs, pe, pa)
+        out[:, :N] -= c * s_e
+        out[:, N:2 * N] -= c * s_a
     out[:, 2 * N] = dy
     if cs.nue.terms & TERM_EMABS:
         _, W = group_energies(cs.nue.e_edge)
@@ -158,6 +244,16 @@ def jacobian_blocks(cs: CoupledSystem, u: np.ndarray):
             et = sys.eta + dy[:, None] * deta
             sign = 1.0 if q == 0 else -1.0
             A[:, 2 * N, sl] = -sign * c * z[:, None] * W[None, :] * (et + ka)
+    if cs.pair_amp is not None:
+        # -c dS_pair/dpsi: own diagonal c [sum Q^p (1 - psibar) + sum Q^a chi psibar], and the cross-species
+        # block c [(1 - psi_k) Q^p_{kk'} + psi_k Q^a_{kk'} chi_{kk'}]
+        qa, qp, qba, qbp = pair_kernels(cs)
+        chi = pair_chi(cs)
+        chib = np.transpose(chi, (0, 2, 1))
+        for (r0, c0, p, pb, qpp, qaa, ch) in ((0, N, pe, pa, qp, qa, chi), (N, 0, pa, pe, qbp, qba, chib)):
+            idx = np.arange(r0, r0 + N)
+            A[:, idx, idx] += c * (np.einsum("ikl,il->ik", qpp, 1.0 - pb) + np.einsum("ikl,il->ik", qaa * ch, pb))
+            A[:, r0:r0 + N, c0:c0 + N] += c * ((1.0 - p)[:, :, None] * qpp + p[:, :, None] * qaa * ch)
     A[:, 2 * N, 2 * N] = 1.0
     if cs.nue.terms & TERM_EMABS:
         dS = lambda q, p: cs.deta_dye[q] * (1.0 - p) - cs.dka_dye[q] * p      # noqa: E731  dS^ea/dY_e
@@ -200,7 +296,20 @@ def rounding_level(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> float:
             mag = mag + c * z * ((np.abs(et * (1.0 - p)) + np.abs(ka * p)) @ W)
     A, _, _ = jacobian_blocks(cs, u)
     mag = mag + np.abs(ye) * np.abs(A[:, 2 * N, 2 * N])
-    return max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(mag)))
+    lev = max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(mag)))
+    if cs.pair_amp is not None:
+        # the pair terms of the species rows, counted as the other source terms are: their magnitudes
+        # plus |psi| times their derivative with respect to the row's own psi
+        qa, qp, qba, qbp = pair_kernels(cs)
+        chi = pair_chi(cs)
+        chib = np.transpose(chi, (0, 2, 1))
+        pe_n, pa_n, _ = unpack(u_n, N)
+        for p, pn, pb, qpp, qaa, ch in ((pe, pe_n, pa, qp, qa, chi), (pa, pa_n, pe, qbp, qba, chib)):
+            cre = np.einsum("ikl,il->ik", qpp, 1.0 - pb)
+            ann = np.einsum("ikl,il->ik", qaa * ch, pb)
+            m = np.abs(p) + np.abs(pn) + c * (np.abs((1.0 - p) * cre) + np.abs(p * ann)) + np.abs(p) * c * (cre + ann)
+            lev = max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(m)))
+    return lev
 
 
 def newton(cs: CoupledSystem, u_n: np.ndarray, u0: Optional[np.ndarray] = None,
@@ -284,6 +393,10 @@ def temperature_update(cs: CoupledSystem, others: list, u: np.ndarray, psi_other
     dy = ye - cs.ye_n
     src = stat_weights[0] * collision_energy_source(cs.nue, pe, cs.dka_dye[0], cs.deta_dye[0], dy)
     src = src + stat_weights[1] * collision_energy_source(cs.nuebar, pa, cs.dka_dye[1], cs.deta_dye[1], dy)
+    if cs.pair_amp is not None:
+        eps, W = group_energies(cs.nue.e_edge)
+        s_e, s_a = pair_sources(cs, pe, pa)
+        src = src + cs.nue.c_dt * (stat_weights[0] * (s_e @ (eps * W)) + stat_weights[1] * (s_a @ (eps * W)))
     for w, sys, p in zip(stat_weights[2:], others, psi_others):
         src = src + w * collision_energy_source(sys, p)
     de = -FOUR_PI_HC3 * M_B_G / cs.rho * src

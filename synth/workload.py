@@ -269,16 +269,21 @@ class YeInputs:
     deta_dye: torch.Tensor
     de_dT: torch.Tensor
     de_dye: torch.Tensor
+    pair_amp: Optional[torch.Tensor] = None    # [R][I] cm^-1, amplitude of the nu_e / anti-nu_e pair kernels
+    pair_g: Optional[torch.Tensor] = None      # [N][N] symmetric pair-kernel shape
+    pair_eta1: Optional[torch.Tensor] = None   # [2][R][I][N] flux factors psi1/psi0 of nu_e, anti-nu_e
 
     def to(self, device):
-        return YeInputs(**{f.name: getattr(self, f.name).to(device) for f in dataclasses.fields(self)})
+        return YeInputs(**{f.name: (None if getattr(self, f.name) is None else getattr(self, f.name).to(device))
+                           for f in dataclasses.fields(self)})
 
     def numpy(self) -> dict:
-        return {f.name: getattr(self, f.name).detach().cpu().numpy() for f in dataclasses.fields(self)}
+        return {f.name: getattr(self, f.name).detach().cpu().numpy() for f in dataclasses.fields(self)
+                if getattr(self, f.name) is not None}
 
 
 def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step: int = 0,
-              R_full: Optional[int] = None) -> YeInputs:
+              R_full: Optional[int] = None, pairs: bool = False) -> YeInputs:
     """Synthetic Y_e-coupling data for workload `w` (made by `make(cfg, rays=rays, step=step, ...)`,
     or by `make_custom(seed_cfg=cfg, R=R_full, ...)` with `R_full` given).
 
@@ -287,7 +292,10 @@ def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step:
     * absorption on free nucleons: kappa_a of nu_e scales with the neutron fraction 1 - Y_e and that
       of anti-nu_e with the proton fraction Y_e, so dkappa_a/dY_e = -kappa_a/(1 - Y_e) and
       +kappa_a/Y_e; the emissivities follow at fixed chemical potentials, deta/dY_e = eta (dkappa_a/dY_e)/kappa_a;
-    * de/dT = 1.5 + 0.5 T/MeV and de/dY_e = -10 T (MeV per baryon): smooth stand-ins for the EoS.
+    * de/dT = 1.5 + 0.5 T/MeV and de/dY_e = -10 T (MeV per baryon): smooth stand-ins for the EoS;
+    * with `pairs`: nu_e / anti-nu_e pair kernels of amplitude 1e-7 (T/10 MeV)^3 cm^-1 and symmetric shape
+      (eps_k eps_k'/(10 MeV)^2) exp(-(ln eps_k - ln eps_k')^2 / (2 0.5^2)), and flux factors
+      psi1/psi0 = x^2/(1 + x^2), x = r / R_nu(eps) (0 deep inside the neutrinosphere, towards 1 outside).
     """
     if w.S < 2:
         raise ValueError("the Y_e coupling needs species 0 (nu_e) and 1 (anti-nu_e)")
@@ -307,7 +315,15 @@ def ye_inputs(w: Workload, cfg: int, rays: Optional[Sequence[int]] = None, step:
     deta = (frac * w.eta[:2]).contiguous()
     de_dT = (1.5 + 0.5 * w.temp).contiguous()
     de_dye = (-10.0 * w.temp).contiguous()
-    return YeInputs(rho=rho, ye_n=ye_n, dka_dye=dka, deta_dye=deta, de_dT=de_dT, de_dye=de_dye)
+    y = YeInputs(rho=rho, ye_n=ye_n, dka_dye=dka, deta_dye=deta, de_dT=de_dT, de_dye=de_dye)
+    if pairs:
+        eps = _group_energies(w.e_edge.to(dev))
+        le = torch.log(eps)
+        g = (eps[:, None] * eps[None, :] / 100.0) * torch.exp(-((le[:, None] - le[None, :]) ** 2) / (2.0 * 0.5 ** 2))
+        x = rc[None, :, :, None] / w.r_nu[:2].to(dev)[:, None, None, :]                # [2][R][I][N]
+        y = dataclasses.replace(y, pair_amp=(1e-7 * (w.temp / 10.0) ** 3).contiguous(), pair_g=g.contiguous(),
+                                pair_eta1=(x * x / (1.0 + x * x)).contiguous())
+    return y
 
 
 @dataclasses.dataclass

@@ -298,16 +298,16 @@ def rounding_level(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> float:
     mag = mag + np.abs(ye) * np.abs(A[:, 2 * N, 2 * N])
     lev = max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(mag)))
     if cs.pair_amp is not None:
-        # the pair terms of the species rows, counted as the other source terms are: their magnitudes
-        # plus |psi| times their derivative with respect to the row's own psi
+        # the pair terms of the species rows, counted as the other source terms are: |psi|, their
+        # magnitudes, and |psi| times their derivative with respect to the row's own psi (|psi^n| is in the
+        # species rows' own level)
         qa, qp, qba, qbp = pair_kernels(cs)
         chi = pair_chi(cs)
         chib = np.transpose(chi, (0, 2, 1))
-        pe_n, pa_n, _ = unpack(u_n, N)
-        for p, pn, pb, qpp, qaa, ch in ((pe, pe_n, pa, qp, qa, chi), (pa, pa_n, pe, qbp, qba, chib)):
+        for p, pb, qpp, qaa, ch in ((pe, pa, qp, qa, chi), (pa, pe, qbp, qba, chib)):
             cre = np.einsum("ikl,il->ik", qpp, 1.0 - pb)
             ann = np.einsum("ikl,il->ik", qaa * ch, pb)
-            m = np.abs(p) + np.abs(pn) + c * (np.abs((1.0 - p) * cre) + np.abs(p * ann)) + np.abs(p) * c * (cre + ann)
+            m = np.abs(p) + c * (np.abs((1.0 - p) * cre) + np.abs(p * ann)) + np.abs(p) * c * (cre + ann)
             lev = max(lev, 32.0 * np.finfo(np.float64).eps * float(np.max(m)))
     return lev
 

@@ -290,6 +290,19 @@ typedef struct {
     const double *dka_dye;   /* [2][R][I][N] cm^-1: dkappa_a/dY_e of species 0 and 1; may be
                                 NULL when TM_TERM_EMABS is off                              */
     const double *deta_dye;  /* [2][R][I][N] cm^-1: deta/dY_e; NULL as dka_dye              */
+    /* Pair creation and annihilation of species 0 and 1 (eqs. d11-d22), optional: NULL
+     * pair_amp turns them off.  Zeroth-moment sources (Phi_0 terms of eq. d14)
+     *   S_0,k = (1 - psi_k) sum_k' Q^p_kk' (1 - pbar_k') - psi_k sum_k' Q^a_kk' chi_kk' pbar_k'
+     * and the same with the species exchanged, Q^a_kk' = a_i g_kk' W_k' / Wbar (Wbar the mean
+     * of W), Q^p = exp(-(eps_k + eps_k')/T_i) Q^a (eq. d12), chi = min(chi_1, chi_2) with
+     * chi_1 = 1 - (3/2) eta_k eta'_k' (the ratio that defines eq. d16, for the flux factors
+     * eta = psi1/psi0 given here) and chi_2 of eq. d19 from the cosines of eq. d22 at the zone
+     * centre (R_nu from tm_inputs.r_nu, which is then required).  The sources join the species
+     * residuals (minus c dt S), the coupled Jacobian (cross-species blocks) and the
+     * temperature update's collision energy.                                            */
+    const double *pair_amp;  /* zone [R][I] cm^-1, kernel amplitude a_i, or NULL           */
+    const double *pair_g;    /* [N][N] symmetric kernel shape g                             */
+    const double *pair_eta1; /* [2][R][I][N] flux factors psi1/psi0 of species 0 and 1      */
 } tm_ye_inputs;
 
 typedef struct {             /* every array is per ray [R], device memory                  */

@@ -302,6 +302,8 @@ tm_status check_ye_inputs(tm_ctx* c, const tm_ye_inputs* y) {
         return set_err(c, TM_ERR_INVALID_ARG, "dka_dye and deta_dye are required when TM_TERM_EMABS is on");
     if (c->p.n_species < 2) return set_err(c, TM_ERR_INVALID_ARG, "the Y_e coupling needs species 0 and 1 (S >= 2)");
     if (c->p.n_groups > tmk::kYeMaxGroups) return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step needs N <= 28");
+    if (y->pair_amp && (!y->pair_g || !y->pair_eta1))
+        return set_err(c, TM_ERR_INVALID_ARG, "pair_amp needs pair_g and pair_eta1");
     return TM_OK;
 }
 
@@ -311,6 +313,9 @@ tmk::YeFields ye_fields_of(const tm_ye_inputs& y) {
     f.ye_n = y.ye_n;
     f.dka = y.dka_dye;
     f.deta = y.deta_dye;
+    f.pair_amp = y.pair_amp;
+    f.pair_g = y.pair_g;
+    f.pair_eta1 = y.pair_eta1;
     return f;
 }
 
@@ -802,6 +807,8 @@ tm_status tm_ye_newton_step(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* 
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     TM_TRY(check_ye_inputs(c, yin));
+    if (yin->pair_amp && !in->r_nu)
+        return set_err(c, TM_ERR_INVALID_ARG, "the pair processes need r_nu (their angular factor uses R_nu)");
     TM_TRY(no_lapse(c, in, "the Y_e-coupled step"));
     if (c->p.precision != TM_PREC_FP64)
         return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step is FP64 only (precision must be TM_PREC_FP64)");
@@ -928,6 +935,8 @@ tm_status tm_temperature_update(tm_ctx* c, const tm_inputs* in, const tm_ye_inpu
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     TM_TRY(check_ye_inputs(c, yin));
+    if (yin->pair_amp && !in->r_nu)
+        return set_err(c, TM_ERR_INVALID_ARG, "the pair processes need r_nu (their angular factor uses R_nu)");
     TM_TRY(no_lapse(c, in, "the temperature update"));
     if (!in->temp) return set_err(c, TM_ERR_INVALID_ARG, "temp (T^n) is required");
     if (!psi || !ye || !stat_weights || !de_dT || !de_dye || !temp_out)

@@ -24,6 +24,7 @@ struct Consts {
     double de[kMaxN];
     double P[kMaxN][kMaxN];
     int nes_window;   // 1 when every group energy is at least 1.25 times the one below it
+    double wbar;      // mean group weight, sum_k W_k / N
 };
 
 struct Shape {
@@ -147,6 +148,21 @@ __device__ __forceinline__ EdgeFlux edge_flux(double u, double v, double lam, do
     f.dHv = 0.5 * dHm + dHd;
     f.dHlam = -3.0 * D * delta * r * r;
     return f;
+}
+
+// Pair processes (eqs. d12, d16-d22).  Cosine of eq. d22 for x = R_nu/R: sqrt(1 - x^2) outside the
+// neutrinosphere, -sqrt(x^2 - 1) clipped at -1 inside it (the equation's sign() read as Fortran's SIGN).
+__device__ __forceinline__ double pair_limb_cosine(double x) {
+    const double v = 1.0 - x * x;
+    return fmax(copysign(sqrt(fabs(v)), v), -1.0);
+}
+// Angular cutoff of the annihilation kernel for a nu of one species and a partner of the other, from
+// their flux factors psi1/psi0 (eta) and limb cosines (mu): chi = min(chi_1, chi_2) (eq. d21), with
+// chi_1 = 1 - (3/2) eta eta' (the ratio that defines eq. d16) and chi_2 of eq. d19; symmetric in the pair.
+__device__ __forceinline__ double pair_chi(double eta, double eta_o, double mu, double mu_o) {
+    const double c1 = 1.0 - 1.5 * eta * eta_o;
+    const double c2 = 0.125 * (8.0 + (mu * mu_o - 3.0) * (1.0 + mu) * (1.0 + mu_o));
+    return fmin(c1, c2);
 }
 
 // Monotone 32-bit key of |v| (sign dropped): for double, the upper word, which orders magnitudes to

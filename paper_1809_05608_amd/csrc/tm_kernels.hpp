@@ -129,6 +129,9 @@ struct YeFields {
     const double* ye_n;
     const double* dka;
     const double* deta;
+    const double* pair_amp;    // [R][I] pair-kernel amplitude, or nullptr (no pair processes)
+    const double* pair_g;      // [N][N] symmetric pair-kernel shape
+    const double* pair_eta1;   // [2][R][I][N] flux factors psi1/psi0 of species 0 and 1
 };
 
 // Per-ray state of the coupled Newton iteration (the same quantities as ResidualOut, per ray).

@@ -39,6 +39,7 @@ __global__ void k_setup(const double* __restrict__ e_edge, const double* __restr
         int ok = 1;
         for (int k = 1; k < N; ++k) ok &= eps[k] >= 1.25 * eps[k - 1];
         out->nes_window = ok;
+        out->wbar = wbar;
     }
     for (int idx = t; idx < kMaxN * kMaxN; idx += blockDim.x) {
         const int k = idx / kMaxN, kp = idx % kMaxN;

@@ -62,14 +62,50 @@ __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFiel
 
     double gmax = 0.0, mag_max = 0.0, lep = 0.0;
     int bad = 0;
+    const bool pair = y.pair_amp != nullptr;
+    __shared__ double s_pair[kBlock / 64][3][64];      // psi, flux factor, limb cosine of both species' groups
+    __shared__ double s_bz[kBlock / 64][NT];           // exp(-eps_j / T) of the zone
     for (int i = wave; i < I; i += kBlock / 64) {
         const double Y = ye[zb + i], Yn = y.ye_n[zb + i];
         const double dy = Y - Yn;
         double sY = 0.0, sAbs = 0.0, sD = 0.0, sL = 0.0;
+        double spair = 0.0;
+        if (pair) {
+            // pair sources of the zone (eqs. d11-d14, Phi_0 terms, chi of eqs. d16-d22)
+            const double Rz = 0.5 * (re[i] + re[i + 1]);
+            double pown = 0.0, eown = 0.0, mown = 0.0;
+            if (real) {
+                const size_t ci = cell0 + (size_t)i * N + kk;
+                pown = psi[ci];
+                eown = y.pair_eta1[ci];
+                mown = pair_limb_cosine(f.r_nu[(size_t)q * N + kk] / Rz);
+            }
+            s_pair[wave][0][lane] = pown;
+            s_pair[wave][1][lane] = eown;
+            s_pair[wave][2][lane] = mown;
+            if (lane < NT) s_bz[wave][lane] = lane < N ? exp(-cs->eps[lane] / f.temp[zb + i]) : 0.0;
+            wave_sync();
+            if (real) {
+                const double a = y.pair_amp[zb + i], iw = 1.0 / cs->wbar, bzk = s_bz[wave][kk];
+                const int o = (1 - q) * NT;
+                double cre = 0.0, ann = 0.0;
+                for (int kp = 0; kp < N; ++kp) {
+                    const double qa = a * y.pair_g[(size_t)kk * N + kp] * cs->W[kp] * iw;
+                    const double pb = s_pair[wave][0][o + kp];
+                    cre = fma(qa * bzk * s_bz[wave][kp], 1.0 - pb, cre);
+                    ann = fma(qa * pair_chi(eown, s_pair[wave][1][o + kp], mown, s_pair[wave][2][o + kp]), pb, ann);
+                }
+                spair = (1.0 - pown) * cre - pown * ann;
+                // rounding level of the pair terms, counted as the other sources are
+                mag_max = fmax(mag_max, fabs(pown) + c * (fabs((1.0 - pown) * cre) + fabs(pown * ann))
+                                            + fabs(pown) * c * (cre + ann));
+            }
+            wave_sync();                               // the rows are rewritten for this wave's next zone
+        }
         if (real) {
             const size_t ci = cell0 + (size_t)i * N + kk;
             const double p = psi[ci];
-            double g = G[ci];
+            double g = G[ci] - c * spair;
             if (emabs) {
                 const double dka = y.dka[ci], det = y.deta[ci];
                 g += c * dy * (dka * p - det * (1.0 - p));              // opacities at Y_e instead of Y_e^n
@@ -150,6 +186,9 @@ struct alignas(16) YeLds {
     double prow[MT + 3];       // pivot row: [0, MT) entries, MT right-hand side, MT+1 diagonal of B
     double bc[2 * NT];         // psi of the zone (both species); x_{i+1} in the backward sweep
     double dd[NT];             // NES neighbour factors exp(-(eps_{j+1} - eps_j)/T)
+    double pe[2 * NT];         // pair processes: flux factors psi1/psi0 of the zone (both species)
+    double pm[2 * NT];         // ... and the limb cosines of eq. d22 at the zone centre
+    double bz[NT];             // ... and exp(-eps_j / T) of the zone
     double yr[2 * NT];         // Y_e row entries, one per species row
     double ys[2 * NT];         // species terms of dG_Y/dY_e
     double fix[MT][MT + 1];    // row-ownership fix-up after pivoting
@@ -171,9 +210,9 @@ __device__ __forceinline__ double lane_value(double v, int p) {
 template <int NT>
 constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
 
-// GEO: the geometric limiter and outer boundary compiled in (instantiated separately, at one wave per SIMD,
-// and launched only for problems that ask for either).
-template <int NT, int WEU, bool GEO>
+// EXT: the geometric limiter and outer boundary and the pair processes compiled in (instantiated
+// separately, at one wave per SIMD, and launched only for problems that ask for any of them).
+template <int NT, int WEU, bool EXT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) void k_ye_factor(YeFactorArgs A) {
     constexpr int MT = 2 * NT + 1;              // rows of a coupled block (<= 57)
     constexpr int NC = 2 * NT;                  // columns of C that can be non-zero (Y_e has bp = 0)
@@ -266,14 +305,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         if (i + 1 < I) {
             const double D_hi = 0.5 * (rhi + re[i + 2]) - 0.5 * (rlo + rhi);
             if (diff && real) {
-                const double limb = (GEO && sh.limiter == 2) ? limb_factor(rhi, A.f.r_nu[(size_t)q * N + kk]) : -1.0;
+                const double limb = (EXT && sh.limiter == 2) ? limb_factor(rhi, A.f.r_nu[(size_t)q * N + kk]) : -1.0;
                 const EdgeFlux e = edge_flux(psi_c, psi_n1, sqrt(lam_c * lam_n1), D_hi, sh.psi_floor, sh.limiter, limb);
                 dHu_hi = e.dHu;
                 dHv_hi = e.dHv;
             }
         } else if (sh.outer_bc == 1) {
             dHu_hi = 1.0;                                   // free streaming: H = psi of the last zone
-        } else if (GEO && sh.outer_bc == 2 && diff && real) {     // ghost zone of eq. a62af
+        } else if (EXT && sh.outer_bc == 2 && diff && real) {     // ghost zone of eq. a62af
             const double rnu = A.f.r_nu[(size_t)q * N + kk];
             const Ghost gh = outer_ghost(rlo, rhi, rnu);
             const EdgeFlux e = edge_flux(psi_c, gh.ratio * psi_c, lam_c, gh.D, sh.psi_floor, sh.limiter,
@@ -302,10 +341,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         }
         ysum = wave_sum(ysum);
         double amp = 0.0;
+        const bool pair = EXT && A.y.pair_amp != nullptr;
         if (nes) {
             amp = az[i];
-            if (lane < NC) L.bc[lane] = real ? psi_c : 0.0;
             if (lane < NT) L.dd[lane] = ws[(size_t)i * (NC + 1) * MT + lane];
+        }
+        if (nes || pair) {
+            if (lane < NC) L.bc[lane] = real ? psi_c : 0.0;
+        }
+        if (pair) {
+            // flux factors, limb cosines (eq. d22) and exp(-eps/T) of the zone for the pair terms
+            const double Rz = 0.5 * (re[i] + re[i + 1]);
+            if (lane < NC) {
+                L.pe[lane] = real ? A.y.pair_eta1[cell0 + (size_t)i * N + kk] : 0.0;
+                L.pm[lane] = real ? pair_limb_cosine(A.f.r_nu[(size_t)q * N + kk] / Rz) : 0.0;
+            }
+            if (lane < NT) L.bz[lane] = lane < N ? exp(-A.cs->eps[lane] / tz[i]) : 0.0;
         }
         wave_sync();
 
@@ -359,6 +410,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         } else if (lane < NC) {
 #pragma unroll
             for (int m = 0; m < MT; ++m) frow[m] = (m == lz) ? 1.0 : 0.0;     // padded identity row
+        }
+        if (pair && real) {
+            // pair processes (eqs. d11-d14): -c dt dS/dpsi, the partner species' block
+            // c [(1 - psi_k) Q^p_kk' + psi_k Q^a_kk' chi_kk'] and the diagonal c sum_k' [Q^p (1 - pbar) + Q^a chi pbar]
+            const double a = A.y.pair_amp[zb + i], iw = 1.0 / A.cs->wbar;
+            const double bzk = L.bz[kk], eo = L.pe[lane], mo = L.pm[lane];
+            const int o = q0 ? NT : 0;
+            double cre = 0.0, ann = 0.0;
+            for (int kp = 0; kp < N; ++kp) {
+                const double qa = a * A.y.pair_g[(size_t)kk * N + kp] * A.cs->W[kp] * iw;
+                const double qp = qa * bzk * L.bz[kp];
+                const double qx = qa * pair_chi(eo, L.pe[o + kp], mo, L.pm[o + kp]);
+                const double pb = L.bc[o + kp];
+                cre = fma(qp, 1.0 - pb, cre);
+                ann = fma(qx, pb, ann);
+                frow[o + kp] += c * ((1.0 - psi_c) * qp + psi_c * qx);
+            }
+            frow[lz] += c * (cre + ann);
         }
         wave_sync();
         // the Y_e row: one entry from every species lane, the diagonal from the sum over them
@@ -587,6 +656,36 @@ __global__ __launch_bounds__(kBlock) void k_ye_temperature(Shape sh, Fields f, Y
         }
         src = fma(wts.w[s], sh.c_dt * acc, src);
     }
+    if (y.pair_amp) {
+        // pair sources of species 0 and 1 (eqs. d11-d14) with their energy weights
+        const double* re = f.r_edge + (size_t)ray * (I + 1);
+        const double Rz = 0.5 * (re[i] + re[i + 1]);
+        const double a = y.pair_amp[idx], iw = 1.0 / cs->wbar;
+        double bz[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bz[j] = j < N ? exp(-cs->eps[j] / T) : 0.0;
+        for (int qs = 0; qs < 2; ++qs) {
+            const size_t co = (((size_t)qs * R + ray) * I + i) * N, cb = (((size_t)(1 - qs) * R + ray) * I + i) * N;
+            double acc = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const double p = psi[co + k], eo = y.pair_eta1[co + k];
+                const double mo = pair_limb_cosine(f.r_nu[(size_t)qs * N + k] / Rz);
+                const double bk = exp(-cs->eps[k] / T);
+                double cre = 0.0, ann = 0.0;
+#pragma unroll
+                for (int kp = 0; kp < NT; ++kp) {
+                    if (kp >= N) break;
+                    const double qa = a * y.pair_g[(size_t)k * N + kp] * cs->W[kp] * iw;
+                    const double pb = psi[cb + kp];
+                    const double mb = pair_limb_cosine(f.r_nu[(size_t)(1 - qs) * N + kp] / Rz);
+                    cre = fma(qa * bk * bz[kp], 1.0 - pb, cre);
+                    ann = fma(qa * pair_chi(eo, y.pair_eta1[cb + kp], mo, mb), pb, ann);
+                }
+                acc = fma(cs->eps[k] * cs->W[k], (1.0 - p) * cre - p * ann, acc);
+            }
+            src = fma(wts.w[qs], sh.c_dt * acc, src);
+        }
+    }
     const double de = -kFourPiOverHc3 * kBaryonMassG / y.rho[idx] * src;
     if (de_out) de_out[idx] = de;
     temp_out[idx] = T + (de - dy * de_dye[idx]) / de_dT[idx];
@@ -619,7 +718,7 @@ hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
     TM_YE_DISPATCH(padded_groups(a.sh.N),
                    constexpr int WPB = ye_waves_per_block<NT>();
                    const long long blocks = (a.nray + WPB - 1) / WPB;
-                   if (a.sh.limiter == 2 || a.sh.outer_bc == 2)
+                   if (a.sh.limiter == 2 || a.sh.outer_bc == 2 || a.y.pair_amp)
                        hipLaunchKernelGGL((k_ye_factor<NT, 1, true>), dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a);
                    else
                        hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>(), false>), dim3((unsigned)blocks),

@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
 
 
 class YeInputs(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("rho", "ye_n", "dka_dye", "deta_dye")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("rho", "ye_n", "dka_dye", "deta_dye", "pair_amp", "pair_g",
+                                               "pair_eta1")]
 
 
 class EadvInputs(ctypes.Structure):
@@ -310,8 +311,18 @@ class Context:
             t = getattr(y, name)
             if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != pair:
                 raise ValueError(f"{name} must be a contiguous float64 tensor of shape {pair} on {self.device}")
+        extra = {}
+        if getattr(y, "pair_amp", None) is not None:
+            self._zone(y.pair_amp, "pair_amp")
+            for name, shape in (("pair_g", (p.n_groups, p.n_groups)), ("pair_eta1", pair)):
+                t = getattr(y, name)
+                if t is None or t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() \
+                        or tuple(t.shape) != shape:
+                    raise ValueError(f"{name} must be a contiguous float64 tensor of shape {shape} on {self.device}")
+            extra = {n: getattr(y, n) for n in ("pair_amp", "pair_g", "pair_eta1")}
         self._keep_ye = y
-        return YeInputs(*[_ptr(getattr(y, n)) for n in ("rho", "ye_n", "dka_dye", "deta_dye")])
+        return YeInputs(*[_ptr(getattr(y, n)) for n in ("rho", "ye_n", "dka_dye", "deta_dye")],
+                        *[_ptr(extra.get(n)) for n in ("pair_amp", "pair_g", "pair_eta1")])
 
     def ye_workspace_bytes(self, batch_rays: int = 0) -> int:
         return int(self.lib.tm_ye_workspace_bytes(ctypes.byref(self.problem), batch_rays))

@@ -35,7 +35,7 @@ TAU = 1e-30
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_F32 = "k_factor_q<20, false, true>"
+KERNEL_F32 = "k_factor_q<20, false, true, 0>"
 
 
 def log(*a):

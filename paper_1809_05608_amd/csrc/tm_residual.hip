@@ -143,7 +143,10 @@ __device__ __forceinline__ double inv_mfp(const Fields& f, size_t c) {
 // kernel computes the rounding level of G (32 ulp of the largest per-cell sum of term
 // magnitudes plus |psi| |dG/dpsi|), below which the Newton stopping rule does not ask for
 // further progress.
-template <int NT, bool LAPSE>
+// LAPSE and GEO compile the lapse factors and the neutrinosphere options (limiter 2, outer boundary 2)
+// in; the plain instance leaves their registers out (127 instead of 131 VGPRs: four waves per SIMD
+// instead of three).
+template <int NT, bool LAPSE, bool GEO>
 __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const Consts* __restrict__ cs,
                                                      const double* __restrict__ psi_n,
                                                      const double* __restrict__ psi, double* __restrict__ G_out,
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     double s_n = 0.0, s_nold = 0.0, s_e = 0.0, s_q = 0.0, s_nes = 0.0, s_b = 0.0;
     const double Wk = lane_ok ? cs->W[k] : 0.0;
     const double epsk = lane_ok ? cs->eps[k] : 0.0;
-    const bool geo = sh.limiter == 2 || sh.outer_bc == 2;       // neutrinosphere radii in use
+    const bool geo = GEO && (sh.limiter == 2 || sh.outer_bc == 2);   // neutrinosphere radii in use
     const double rnuk = (geo && lane_ok) ? f.r_nu[(size_t)(sys / sh.R) * N + k] : 0.0;
     const double dek = (lane_ok && k + 1 < N) ? cs->de[k] : 0.0;
     const size_t sys_cell0 = (size_t)sys * I * N;
@@ -257,14 +260,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
                         const double D = 0.5 * (rhi + rp) - 0.5 * (rlo + rhi);
                         const EdgeFlux e = edge_flux(p, s_psi[zl + 1][k], sqrt(lam * s_lam[zl + 1][k]), D,
                                                      sh.psi_floor, sh.limiter,
-                                                     sh.limiter == 2 ? limb_factor(rhi, rnuk) : -1.0);
+                                                     (GEO && sh.limiter == 2) ? limb_factor(rhi, rnuk) : -1.0);
                         H = e.H;
                         du = e.dHu;
                         dv = e.dHv;
                     } else if (sh.outer_bc == 1) {
                         H = p;                              // free streaming, eq. a22 limit
                         du = 1.0;
-                    } else if (sh.outer_bc == 2) {          // ghost zone of eq. a62af
+                    } else if (GEO && sh.outer_bc == 2) {   // ghost zone of eq. a62af
                         const double rlo = s_re[zl], rhi = s_re[zl + 1];
                         const Ghost gh = outer_ghost(rlo, rhi, rnuk);
                         const EdgeFlux e = edge_flux(p, gh.ratio * p, lam, gh.D, sh.psi_floor, sh.limiter,
@@ -835,14 +838,18 @@ hipError_t launch_residual(const Shape& sh, const Fields& f, const Consts* cs, c
                            const double* psi, double* G_out, double g_sign, const ResidualOut& out,
                            hipStream_t st) {
     const long long nsys = (long long)sh.S * sh.R;
-    if (f.lapse) {
+    if (sh.limiter == 2 || sh.outer_bc == 2) {
         TM_DISPATCH_NT(padded_groups(sh.N),
-                       hipLaunchKernelGGL((k_residual<NT, true>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f,
-                                          cs, psi_n, psi, G_out, g_sign, out));
+                       hipLaunchKernelGGL((k_residual<NT, true, true>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh,
+                                          f, cs, psi_n, psi, G_out, g_sign, out));
+    } else if (f.lapse) {
+        TM_DISPATCH_NT(padded_groups(sh.N),
+                       hipLaunchKernelGGL((k_residual<NT, true, false>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh,
+                                          f, cs, psi_n, psi, G_out, g_sign, out));
     } else {
         TM_DISPATCH_NT(padded_groups(sh.N),
-                       hipLaunchKernelGGL((k_residual<NT, false>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, f,
-                                          cs, psi_n, psi, G_out, g_sign, out));
+                       hipLaunchKernelGGL((k_residual<NT, false, false>), dim3((unsigned)nsys), dim3(kBlock), 0, st, sh,
+                                          f, cs, psi_n, psi, G_out, g_sign, out));
     }
     return hipGetLastError();
 }

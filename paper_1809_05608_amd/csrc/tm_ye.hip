@@ -38,7 +38,9 @@ __device__ __forceinline__ double ye_zeta(double rho) { return kFourPiOverHc3 * 
 
 // ---------------------------------------------------------------- residual completion and decisions
 
-template <int NT>
+// PAIR compiles the pair sources in (their loops double the kernel's registers); the launch takes it
+// when pair inputs are given.
+template <int NT, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFields y, const Consts* __restrict__ cs,
                                                       const double* __restrict__ psi, const double* __restrict__ ye,
                                                       double* __restrict__ G, double* __restrict__ GY,
@@ -62,9 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFiel
 
     double gmax = 0.0, mag_max = 0.0, lep = 0.0;
     int bad = 0;
-    const bool pair = y.pair_amp != nullptr;
-    __shared__ double s_pair[kBlock / 64][3][64];      // psi, flux factor, limb cosine of both species' groups
-    __shared__ double s_bz[kBlock / 64][NT];           // exp(-eps_j / T) of the zone
+    const bool pair = PAIR && y.pair_amp != nullptr;
+    __shared__ double s_pair[PAIR ? kBlock / 64 : 1][3][64];   // psi, flux factor, limb cosine of both species' groups
+    __shared__ double s_bz[PAIR ? kBlock / 64 : 1][NT];        // exp(-eps_j / T) of the zone
     for (int i = wave; i < I; i += kBlock / 64) {
         const double Y = ye[zb + i], Yn = y.ye_n[zb + i];
         const double dy = Y - Yn;
@@ -708,9 +710,14 @@ __global__ __launch_bounds__(kBlock) void k_ye_temperature(Shape sh, Fields f, Y
 hipError_t launch_ye_couple(const Shape& sh, const Fields& f, const YeFields& y, const Consts* cs, const double* psi,
                             const double* ye, double* G, double* GY, const double* level_sp, const YeOut& out,
                             hipStream_t st) {
-    TM_YE_DISPATCH(padded_groups(sh.N),
-                   hipLaunchKernelGGL(k_ye_couple<NT>, dim3((unsigned)sh.R), dim3(kBlock), 0, st, sh, f, y, cs, psi, ye,
-                                      G, GY, level_sp, out))
+    if (y.pair_amp)
+        TM_YE_DISPATCH(padded_groups(sh.N),
+                       hipLaunchKernelGGL((k_ye_couple<NT, true>), dim3((unsigned)sh.R), dim3(kBlock), 0, st, sh, f, y, cs,
+                                          psi, ye, G, GY, level_sp, out))
+    else
+        TM_YE_DISPATCH(padded_groups(sh.N),
+                       hipLaunchKernelGGL((k_ye_couple<NT, false>), dim3((unsigned)sh.R), dim3(kBlock), 0, st, sh, f, y,
+                                          cs, psi, ye, G, GY, level_sp, out))
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct tm_ctx {
     int* y_flags = nullptr;
     int* y_pending = nullptr;
     int* y_backtrack = nullptr;
+    int* y_redo = nullptr;       // rays of the tiled diagonal-pivot launch sent to partial pivoting
     // inputs with the lapse folded in (allocated on first use with a lapse)
     double* lp_ka = nullptr;
     double* lp_et = nullptr;
@@ -263,6 +264,7 @@ tm_status ensure_ye(tm_ctx* c) {
     TM_TRY(ial(&c->y_flags, R, "hipMalloc y_flags"));
     TM_TRY(ial(&c->y_pending, R, "hipMalloc y_pending"));
     TM_TRY(ial(&c->y_backtrack, R, "hipMalloc y_backtrack"));
+    TM_TRY(ial(&c->y_redo, R, "hipMalloc y_redo"));
     return TM_OK;
 }
 
@@ -528,7 +530,7 @@ tm_status tm_destroy(tm_ctx* c) {
         for (double* p : {c->y_res, c->y_res0, c->y_res_acc, c->y_tgt, c->y_alpha, c->y_res_sp, c->y_lev, c->y_gy,
                           c->y_dy})
             (void)hipFree(p);
-        for (int* p : {c->y_active, c->y_iters, c->y_flags, c->y_pending, c->y_backtrack}) (void)hipFree(p);
+        for (int* p : {c->y_active, c->y_iters, c->y_flags, c->y_pending, c->y_backtrack, c->y_redo}) (void)hipFree(p);
     }
     for (double* p : {c->lp_ka, c->lp_et, c->lp_ks, c->lp_temp, c->lp_amp})
         if (p) (void)hipFree(p);
@@ -886,15 +888,35 @@ tm_status tm_ye_newton_step(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* 
     a.pending = c->y_pending;
     a.alpha = c->y_alpha;
     a.ws = static_cast<double*>(c->ws);
+    a.growth_limit = c->growth_limit;
+    // Diagonal pivots on lane tiles, with the rays the growth guard sends back re-run with partial
+    // pivoting (TM_PIVOT=always: partial pivoting only; =never: a guard trip is an error).  The
+    // neutrinosphere options and the pair processes take the partial-pivoting kernel.
+    const bool tiled = c->pivot_policy != 1 && tmk::ye_tiled_applies(a);
     const int max_trials = 9;                              // alpha = 1, 1/2, ..., 1/256
     for (int it = 0; it < max_iter; ++it) {
         int nact = 0;
         TM_TRY(count_of(c->y_active, &nact));
         if (nact == 0) break;
+        if (tiled && c->pivot_policy == 2)
+            TM_TRY(hip_check(c, tmk::launch_fill_i32(c->y_redo, R, 0, c->stream), "fill kernel"));
         for (long long r0 = 0; r0 < R; r0 += batch) {
             a.ray0 = r0;
             a.nray = std::min(batch, R - r0);
-            TM_TRY(hip_check(c, tmk::launch_ye_factor(a, c->stream), "coupled factor kernel"));
+            if (tiled) {
+                a.redo = c->y_redo;
+                TM_TRY(hip_check(c, tmk::launch_ye_factor_tiled(a, c->stream), "coupled tiled factor kernel"));
+                if (c->pivot_policy != 2)        // the marked rays of this batch, with partial pivoting
+                    TM_TRY(hip_check(c, tmk::launch_ye_factor(a, c->stream), "coupled factor kernel"));
+            } else {
+                a.redo = nullptr;
+                TM_TRY(hip_check(c, tmk::launch_ye_factor(a, c->stream), "coupled factor kernel"));
+            }
+        }
+        if (tiled && c->pivot_policy == 2) {
+            int nredo = 0;
+            TM_TRY(count_of(c->y_redo, &nredo));
+            if (nredo > 0) return set_err(c, TM_ERR_SINGULAR, "diagonal-pivot growth guard tripped in the coupled step");
         }
         for (int t = 0; t < max_trials; ++t) {
             TM_TRY(evaluate(tmk::kResTrial));

@@ -173,6 +173,11 @@ struct YeFactorArgs {
     double* ws;               // per ray slot: I * (2 NT + 1) * (2 NT + 1) doubles
     long long ray0;           // first ray of the batch
     long long nray;           // rays in the batch
+    // Diagonal pivots on 8 x 8 lane tiles (launch_ye_factor_tiled): a ray whose multipliers exceed
+    // growth_limit, or that meets a zero or non-finite pivot, is left untouched and marked in redo;
+    // the partial-pivoting launch (launch_ye_factor) with redo set then takes only the marked rays.
+    int* redo = nullptr;      // per ray (nullable for the partial-pivoting launch: all active rays)
+    double growth_limit = 16.0;
 };
 
 // Species residual G (from the single-species residual pass, opacities at Y_e^n) completed in place
@@ -182,6 +187,9 @@ hipError_t launch_ye_couple(const Shape& sh, const Fields& f, const YeFields& y,
                             const double* ye, double* G, double* GY, const double* level_sp, const YeOut& out,
                             hipStream_t st);
 hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st);
+// false when the problem needs the partial-pivoting kernel only (neutrinosphere options or pairs)
+bool ye_tiled_applies(const YeFactorArgs& a);
+hipError_t launch_ye_factor_tiled(const YeFactorArgs& a, hipStream_t st);
 // psi (species 0, 1) and ye += (alpha/2 - alpha) delta, alpha /= 2, for rays with backtrack set (cleared)
 hipError_t launch_ye_backtrack(const Shape& sh, double* psi, double* ye, const double* dx, const double* dY,
                                int* backtrack, double* alpha, hipStream_t st);

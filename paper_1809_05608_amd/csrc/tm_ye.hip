@@ -19,7 +19,10 @@
 //                     as a max over the wavefront, pivot row read from the pivot lane into scalar
 //                     registers) produces
 //                     C_i = Ahat_i^{-1} diag(bp_i) and y_i; the backward sweep x_i = y_i - C_i x_{i+1}
-//                     applies the Newton update.
+//                     applies the Newton update.  The default instance (TILE) eliminates with diagonal
+//                     pivots instead, the block spread over 8 x 8 lane tiles, so each step moves 2 T
+//                     values per lane through LDS instead of M + 1 broadcasts; a ray that trips its growth
+//                     guard is left untouched and re-run by the partial-pivoting instance.
 //   k_ye_backtrack    line-search move-back of rejected trials.
 //   k_ye_temperature  one thread per zone: energy-weighted collision sources of every species, the
 //                     matter energy change and the new temperature.
@@ -193,8 +196,13 @@ struct alignas(16) YeLds {
     double bz[NT];             // ... and exp(-eps_j / T) of the zone
     double yr[2 * NT];         // Y_e row entries, one per species row
     double ys[2 * NT];         // species terms of dG_Y/dY_e
-    double fix[MT][MT + 1];    // row-ownership fix-up after pivoting
+    double fix[MT][MT + 1];    // row-ownership fix-up after pivoting; the rows between zones
     int plane[MT];             // pivot lane of each elimination step
+    // tiled elimination: pivot row (entries, then g) and pivot column of each step, double-buffered
+    double urow[2][8 * ((MT + 8) / 8)];
+    double ucol[2][8 * ((MT + 8) / 8)];
+    double bpv[MT];            // B coefficient of every row
+    double pivs[MT];           // pivot of every step
 };
 
 template <int NT>
@@ -212,9 +220,100 @@ __device__ __forceinline__ double lane_value(double v, int p) {
 template <int NT>
 constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
 
+// In-place Gauss-Jordan on [Ahat | diag(bp) | g] with diagonal pivots, the block and g spread over the
+// wavefront as 8 x 8 tiles of T x T entries (T = ceil((MT + 1) / 8), g being column MT): lane 8 a + b holds
+// rows T a .. T a + T - 1 and columns T b .. T b + T - 1.  Step cc needs, in each lane, the pivot row's
+// entries of its columns and the pivot column's entries of its rows: the lanes holding them put them in
+// LDS (T values per lane, double-buffered between steps) and every lane reads its 2 T values back,
+// instead of all M + 1 values of the pivot row.  Column cc becomes column cc of C = Ahat^-1 diag(bp) as
+// in the row-per-lane elimination; each row is divided by its pivot at the end.  Reads the rows and g
+// from L.fix, the B coefficients from L.bpv; writes C and y back to L.fix in natural order.  bad is set
+// for a multiplier above limit (growth guard) or a zero or non-finite pivot.
+template <int MT, typename Lds>
+__device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, bool& bad) {
+    constexpr int T = (MT + 8) / 8;
+    // the lane id through an opaque copy: the lane masks of the steps are then formed per zone instead of
+    // being hoisted out of the zone loop into scalar registers held across the row assembly
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    const int ta = lo >> 3, tb = lo & 7;
+    double t[T][T];
+    double gmax = 0.0;
+#pragma unroll
+    for (int tr = 0; tr < T; ++tr) {
+        const int r = T * ta + tr;
+#pragma unroll
+        for (int tc = 0; tc < T; ++tc) {
+            const int c = T * tb + tc;
+            const bool in = r < MT && c <= MT;
+            t[tr][tc] = in ? L.fix[in ? r : 0][in ? c : 0] : ((r == c && c != MT) ? 1.0 : 0.0);   // padding: identity
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < MT; ++cc) {
+        const int ap = cc / T, rp = cc % T;            // tile row and column of the pivot: lane 9 ap, (rp, rp)
+        double* const ur = L.urow[cc & 1];
+        double* const uc = L.ucol[cc & 1];
+        if (ta == ap) {
+#pragma unroll
+            for (int tc = 0; tc < T; ++tc) ur[T * tb + tc] = t[rp][tc];
+        }
+        if (tb == ap) {
+#pragma unroll
+            for (int tr = 0; tr < T; ++tr) uc[T * ta + tr] = t[tr][rp];
+        }
+        wave_sync();
+        const double piv = ur[cc], bpiv = L.bpv[cc];
+        const double pinv = drcp(piv);
+        if (lane == 0) L.pivs[cc] = piv;
+        double u[T], f[T];
+#pragma unroll
+        for (int tc = 0; tc < T; ++tc) u[tc] = ur[T * tb + tc];
+#pragma unroll
+        for (int tr = 0; tr < T; ++tr) {
+            f[tr] = uc[T * ta + tr] * pinv;
+            if (tr == rp && ta == ap) f[tr] = 0.0;     // the pivot row itself
+            gmax = fmax(gmax, fabs(f[tr]));
+        }
+#pragma unroll
+        for (int tr = 0; tr < T; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < T; ++tc) t[tr][tc] = fma(-f[tr], u[tc], t[tr][tc]);
+        if (tb == ap) {                                // column cc: -f bp_cc, and bp_cc in the pivot row
+#pragma unroll
+            for (int tr = 0; tr < T; ++tr) t[tr][rp] = (tr == rp && ta == ap) ? bpiv : -f[tr] * bpiv;
+        }
+        // every entry is materialised at the end of its step: left alone, the compiler sinks each update to
+        // the entry's next use and holds every earlier step's multipliers and pivot-row values live
+#pragma unroll
+        for (int tr = 0; tr < T; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < T; ++tc) asm volatile("" : "+v"(t[tr][tc]));
+        asm volatile("" : "+v"(gmax));
+    }
+    bad |= !(gmax <= limit);
+    wave_sync();                                       // pivs[] is read by other lanes
+#pragma unroll
+    for (int tr = 0; tr < T; ++tr) {
+        const int r = T * ta + tr;
+        if (r >= MT) continue;
+        const double pv = L.pivs[r];
+        bad |= !(fabs(pv) > 0.0) || !isfinite(pv);
+        const double ip = drcp(pv);
+#pragma unroll
+        for (int tc = 0; tc < T; ++tc) {
+            const int c = T * tb + tc;
+            if (c <= MT) L.fix[r][c] = t[tr][tc] * ip;
+        }
+    }
+    wave_sync();
+}
+
 // EXT: the geometric limiter and outer boundary and the pair processes compiled in (instantiated
 // separately, at one wave per SIMD, and launched only for problems that ask for any of them).
-template <int NT, int WEU, bool EXT>
+// TILE: the elimination with diagonal pivots on 8 x 8 lane tiles (below) instead of partial pivoting
+// with one row per lane.
+template <int NT, int WEU, bool EXT, bool TILE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) void k_ye_factor(YeFactorArgs A) {
     constexpr int MT = 2 * NT + 1;              // rows of a coupled block (<= 57)
     constexpr int NC = 2 * NT;                  // columns of C that can be non-zero (Y_e has bp = 0)
@@ -231,6 +330,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     if (rb >= A.nray) return;                                          // whole wave (no block barrier follows)
     const long long ray = A.ray0 + rb;
     if (A.active && A.active[ray] == 0) return;
+    if (!TILE && A.redo && A.redo[ray] == 0) return;                   // the re-run takes marked rays only
 
     YeLds<NT>& L = lds_all[wave];
     const Shape& sh = A.sh;
@@ -437,14 +537,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         if (isY) L.fix[NC][NC] = emabs ? 1.0 + c * z * ysum : 1.0;
         wave_sync();
 
-        // ---- (2) elimination in registers
-        double a[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = is_row ? frow[m] : 0.0;
         double g = 0.0;
         if (real) g = fma(-bm, ycar, A.rhs_sign * rhs[(size_t)i * N + kk]);
         else if (isY) g = A.rhs_sign * A.GY[zb + i];
         const double bcoef = bp;
+        if constexpr (TILE) {
+            if (is_row) {
+                frow[MT] = g;                          // y_{i-1} was consumed above
+                L.bpv[kr] = bcoef;
+            }
+            wave_sync();
+            tile_eliminate<MT>(L, lane, A.growth_limit, zp);
+        } else {
+        // ---- (2) elimination in registers
+        double a[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = is_row ? frow[m] : 0.0;
 
         // in-place Gauss-Jordan on [Ahat | diag(bp) | g], partial pivoting over the wavefront
         // (the step loop must be fully unrolled: a[cc] with a run-time cc would put the row in scratch)
@@ -493,12 +601,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             dst[MT] = g * ip;
         }
         wave_sync();
+        }
 
         psi_c = psi_n1;
         sig_c = sig_n1;
         lam_c = lam_n1;
         dHu_lo = dHu_hi;
         dHv_lo = dHv_hi;
+    }
+    if constexpr (TILE) {
+        // growth guard: a ray with a multiplier above the limit or a zero pivot is left untouched and
+        // marked for the partial-pivoting re-run
+        const bool bad = __ballot(zp) != 0ull;
+        if (lane == 0 && A.redo) A.redo[ray] = bad ? 1 : 0;
+        if (bad) return;
     }
     if (is_row) {                                      // C_{I-1}, y_{I-1}
         double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + lane;
@@ -512,6 +628,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     int lb;
     asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lb));
     const int kb = lb < MT ? lb : 0;
+    // the cell offset of the lane's row likewise
+    const int qb = lb < NT ? 0 : 1, kgb = lb - qb * NT;
+    const bool realb = lb < NC && kgb < N;
+    const size_t cellb = ((size_t)(realb ? qb : 0) * R + ray) * I * N + (realb ? kgb : 0);
     double cr[NC], crn[NC];
     double yv = 0.0, yn = 0.0;
     {
@@ -536,11 +656,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             for (int m = 0; m < NC; ++m) dl = fma(-cr[m], L.bc[m], dl);
             wave_sync();
         }
-        if (real) {
-            const size_t ci = cell0 + (size_t)i * N + kk;
+        if (realb) {
+            const size_t ci = cellb + (size_t)i * N;
             A.psi_out[ci] += dl;
             A.dx[ci] = dl;
-        } else if (isY) {
+        } else if (lb == NC) {
             A.ye_out[zb + i] += dl;
             A.dY[zb + i] = dl;
         }
@@ -725,11 +845,24 @@ hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
     TM_YE_DISPATCH(padded_groups(a.sh.N),
                    constexpr int WPB = ye_waves_per_block<NT>();
                    const long long blocks = (a.nray + WPB - 1) / WPB;
-                   if (a.sh.limiter == 2 || a.sh.outer_bc == 2 || a.y.pair_amp)
-                       hipLaunchKernelGGL((k_ye_factor<NT, 1, true>), dim3((unsigned)blocks), dim3(64 * WPB), 0, st, a);
+                   if (!ye_tiled_applies(a))
+                       hipLaunchKernelGGL((k_ye_factor<NT, 1, true, false>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
+                                          st, a);
                    else
-                       hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>(), false>), dim3((unsigned)blocks),
+                       hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>(), false, false>), dim3((unsigned)blocks),
                                           dim3(64 * WPB), 0, st, a))
+    return hipGetLastError();
+}
+
+bool ye_tiled_applies(const YeFactorArgs& a) { return !(a.sh.limiter == 2 || a.sh.outer_bc == 2 || a.y.pair_amp); }
+
+hipError_t launch_ye_factor_tiled(const YeFactorArgs& a, hipStream_t st) {
+    if (!ye_tiled_applies(a) || !a.redo) return hipErrorInvalidValue;
+    TM_YE_DISPATCH(padded_groups(a.sh.N),
+                   constexpr int WPB = ye_waves_per_block<NT>();
+                   const long long blocks = (a.nray + WPB - 1) / WPB;
+                   hipLaunchKernelGGL((k_ye_factor<NT, ye_waves_per_eu<NT>(), false, true>), dim3((unsigned)blocks),
+                                      dim3(64 * WPB), 0, st, a))
     return hipGetLastError();
 }
 

@@ -3,8 +3,9 @@
 temperature update, batching over a caller workspace, and argument checks.
 
 Metric for psi: the difference relative to the largest occupation of the same zone and species,
-max_k |psi| (floored at tau).  The coupled block is eliminated with partial pivoting, so rounding
-enters every cell of a zone at the scale of that zone's largest entries; cells 30 decades below
+max_k |psi| (floored at tau).  The coupled block is eliminated as a whole (diagonal pivots on lane
+tiles, or partial pivoting for the rays the growth guard sends back), so rounding enters every cell
+of a zone at the scale of that zone's largest entries; cells 30 decades below
 it (the high-energy tail of cold zones) carry that absolute rounding, not a relative one.  Two
 FP64 oracle routes (the 2N+1 block against the N blocks in the decoupled limit) differ by about
 1e-31 under this metric.  Y_e is compared relative to its largest value.  Bar: 1e-12 (FP64).
@@ -103,6 +104,31 @@ def test_coupled_newton_fixed_updates_match_oracle(shape):
     assert np.all(stats["iters"] == 3)
     if w.S > 2:
         np.testing.assert_array_equal(psi[2:], psi0[2:])      # the uncoupled species are not touched
+
+
+PIVOT_ENVS = [dict(TM_PIVOT="never"), dict(TM_GROWTH_LIMIT="0"), dict(TM_PIVOT="always")]
+
+
+@pytest.mark.parametrize("env", PIVOT_ENVS, ids=["tiled-only", "all-rays-rerun", "partial-pivoting-only"])
+@pytest.mark.parametrize("shape", [SHAPES[0], SHAPES[1], SHAPES[3], SHAPES[4]])
+def test_elimination_paths_match_oracle(shape, env, monkeypatch):
+    """The three elimination paths of the coupled block, forced from the host, against the oracle: the
+    tiled diagonal-pivot kernel alone (TM_PIVOT=never: a growth-guard trip would be an error), every ray
+    sent back to partial pivoting by the guard (TM_GROWTH_LIMIT=0), and partial pivoting only."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    say("case ye elimination path", env, shape)
+    w, y = _case(**shape)
+    rng = np.random.default_rng(23)
+    psi0 = (w.psi_n.numpy() * rng.uniform(0.9, 1.1, w.psi_n.shape)).clip(0, 1)
+    ye0 = y.ye_n.numpy() + 0.003 * rng.standard_normal(y.ye_n.shape)
+    st, psi, ye, stats = _gpu(w, y, 3, 0.0, psi0, ye0)
+    assert st == tm.TM_OK
+    ora = _oracle(w, y, 3, 0.0, psi0, ye0)
+    e, ey = _compare(w, psi, ye, ora)
+    say("  psi err", e, "ye err", ey)
+    assert e < BAR and ey < BAR
+    assert np.all(stats["iters"] == 3)
 
 
 @pytest.mark.parametrize("shape", [dict(S=2, R=16, I=64, N=12), dict(S=2, R=4, I=24, N=20)])

@@ -599,40 +599,39 @@ def adjoint(sys: System, psi: np.ndarray, seed: np.ndarray, solver: str = "dense
 def param_vjp(sys: System, psi: np.ndarray, mu: np.ndarray) -> dict:
     """-mu^T dG/dtheta for theta in (kappa_a, eta, kappa_s, nes_amp, psi_n).
 
-    dG/dkappa_a = c dt psi and dG/deta = -c dt (1 - psi) on the own cell (eq. a54 form);
-    all three opacities also reach G_{i-1}, G_i, G_{i+1} through lambda_i, the edge
-    means lambda_{i+-1/2} = sqrt(lambda_i lambda_{i+-1}) and the edge fluxes (eq. a59),
-    with d lambda_e / d chi_i = -lambda_e lambda_i / 2 for chi = 1/lambda;
-    dG/d amp_i = -c dt S_{i,k}/amp_i; dG/dpsi^n = -1.
+    dG/dkappa_a = c dt a_i psi and dG/deta = -c dt a_i (1 - psi) on the own cell (eq. a54 form
+    times the lapse a_i of eq. a58, a = 1 without one); all three opacities also reach G_{i-1},
+    G_i, G_{i+1} through lambda_i, the edge means lambda_{i+-1/2} = sqrt(lambda_i lambda_{i+-1})
+    and the edge fluxes (eq. a59), with d lambda_e / d chi_i = -lambda_e lambda_i / 2 for
+    chi = 1/lambda, each edge weighted by a^3/V of the zone and A/a^2 of the edge;
+    dG/d amp_i = -c dt a_i S_{i,k}/amp_i; dG/dpsi^n = -1.
     """
-    if sys.lapse is not None:
-        raise NotImplementedError("the parameter VJP is written for a = 1 (the device adjoint takes no lapse)")
     I, N = psi.shape
-    _, V, A, _ = geometry(sys.r_edge)
+    vf, Aw, a = _weights(sys)         # a^3 / V per zone, A / a^2 per edge, a per zone
     c = sys.c_dt
     lam = _lambda(sys)
     g_chi = np.zeros((I, N))      # mu-weighted dG/dchi_i through the edge fluxes
     if sys.terms & TERM_DIFFUSION:
         _, _, _, dHl, lam_e = _edge_fluxes(sys, psi)
         for e in range(1, I):          # interior edge between zones e-1 and e
-            # G_{e-1} += c A_e H_e / V_{e-1};  G_e -= c A_e H_e / V_e
-            w = c * A[e] * (mu[e - 1] / V[e - 1] - mu[e] / V[e])     # mu-weighted dG/dH_e
+            # G_{e-1} += c (A/a^2)_e H_e (a^3/V)_{e-1};  G_e -= c (A/a^2)_e H_e (a^3/V)_e
+            w = c * Aw[e] * (mu[e - 1] * vf[e - 1] - mu[e] * vf[e])     # mu-weighted dG/dH_e
             for zone in (e - 1, e):
                 dlam_dchi = -0.5 * lam_e[e] * lam[zone]
                 g_chi[zone] += w * dHl[e] * dlam_dchi
         # the geometric outer boundary's flux carries the last zone's mean free path (lam_e = lam_I)
-        w_out = c * A[I] * mu[I - 1] / V[I - 1]
+        w_out = c * Aw[I] * mu[I - 1] * vf[I - 1]
         g_chi[I - 1] += w_out * dHl[I] * (-lam[I - 1] * lam[I - 1])
     g_ka = g_chi.copy()
     g_eta = g_chi.copy()
     g_ks = g_chi.copy()
     if sys.terms & TERM_EMABS:
-        g_ka += mu * c * psi
-        g_eta += mu * (-c * (1.0 - psi))
+        g_ka += mu * c * a[:, None] * psi
+        g_eta += mu * (-c * a[:, None] * (1.0 - psi))
     g_amp = np.zeros(I)
     if sys.terms & TERM_NES:
         S1 = nes_source(sys, psi, unit_amplitude=True)
-        g_amp = np.sum(mu * (-c * S1), axis=1)
+        g_amp = np.sum(mu * (-c * a[:, None] * S1), axis=1)
     return dict(kappa_a=-g_ka, eta=-g_eta, kappa_s=-g_ks, nes_amp=-g_amp, psi_n=mu.copy())
 
 

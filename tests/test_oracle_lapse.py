@@ -138,3 +138,77 @@ def test_jacobian_with_lapse_matches_central_differences(terms):
         gm = tr.residual(sys, psi, psi - d.reshape(psi.shape)).ravel()
         Jfd[:, m] = (gp - gm) / (2 * d[m])
     assert np.allclose(J, Jfd, rtol=1e-6, atol=1e-8 * np.abs(J).max())
+
+
+def _lapse_gradient_mismatch(sys, psin, names=("kappa_a", "eta", "kappa_s", "nes_amp", "psi_n"), seed=9):
+    """Largest |adjoint - central difference| of dL/dtheta along random relative directions, relative to
+    the adjoint value (plus a floor of 1e-9 L)."""
+    import dataclasses
+
+    def solve(sy, pn):
+        return tr.newton(sy, pn, max_iter=40, rtol=1e-15).psi
+
+    psi = solve(sys, psin)
+    mu = tr.adjoint(sys, psi, tr.luminosity_seed(sys, psi.shape))
+    g = tr.param_vjp(sys, psi, mu)
+    L0 = tr.luminosity(sys, psi)
+    r = np.random.default_rng(seed)
+    h = 1e-6
+    worst = 0.0
+    for name in names:
+        for _ in range(2):
+            base = psin if name == "psi_n" else getattr(sys, name)
+            d = r.standard_normal(base.shape) * base
+
+            def L(sign):
+                if name == "psi_n":
+                    return tr.luminosity(sys, solve(sys, psin + sign * h * d))
+                sy = dataclasses.replace(sys, **{name: base + sign * h * d})
+                return tr.luminosity(sy, solve(sy, psin))
+
+            fd = (L(+1) - L(-1)) / (2 * h)
+            an = float(np.sum(g[name] * d))
+            worst = max(worst, abs(fd - an) / (abs(an) + 1e-9 * abs(L0) / 1e-5))
+    return worst
+
+
+def _lapse_gradient_case():
+    sys = make_system(I=10, N=6, seed=6, c_dt=3e4, r_span=20.0)
+    import dataclasses
+    sys = dataclasses.replace(sys, kappa_a=sys.kappa_a * 3e3, eta=sys.eta * 3e3, kappa_s=sys.kappa_s * 3e3,
+                              nes_amp=sys.nes_amp * 3e5)
+    r = np.random.default_rng(7)
+    psin = r.uniform(0.05, 0.6, (sys.I, sys.N))
+    return sys, psin
+
+
+def test_luminosity_gradient_with_lapse_matches_central_differences():
+    """dL/dtheta of the lapsed luminosity L = c A_{I+1/2}/a_{I+1/2}^2 sum_k W_k H (eq. a62 with eq. a58's
+    lapse) from the adjoint, J^T mu = dL/dpsi and g = -mu^T dG/dtheta, equals central differences of
+    L(psi^{n+1}(theta)) for kappa_a, eta, kappa_s, the NES amplitude and psi^n."""
+    sys, psin = _lapse_gradient_case()
+    assert np.ptp(sys.lapse) > 0.1                               # the lapse varies across the grid
+    assert _lapse_gradient_mismatch(sys, psin) < 1e-5
+
+
+def test_lapse_gradient_pin_catches_a_missing_source_lapse(monkeypatch):
+    """Plant the parameter VJP without the lapse on the emission/absorption and NES terms (the a = 1
+    form): the central-difference pin must fail."""
+    orig = tr._weights
+
+    def no_source_lapse(sys):
+        vf, Aw, a = orig(sys)
+        return vf, Aw, np.ones_like(a)
+
+    sys, psin = _lapse_gradient_case()
+    real_vjp = tr.param_vjp
+
+    def planted(sy, psi, mu):
+        monkeypatch.setattr(tr, "_weights", no_source_lapse)
+        try:
+            return real_vjp(sy, psi, mu)
+        finally:
+            monkeypatch.setattr(tr, "_weights", orig)
+
+    monkeypatch.setattr(tr, "param_vjp", planted)
+    assert _lapse_gradient_mismatch(sys, psin, names=("kappa_a", "nes_amp")) > 1e-3

@@ -147,8 +147,10 @@ typedef struct {
  * The statistics become: number sum_i V_i / a_i^3 sum_k W_k psi, energy at infinity with the same
  * weights, outer flux c A_{I+1/2} / a_{I+1/2}^2 sum_k W_k H.  tm_assemble, tm_factor_solve and
  * tm_newton_step take a lapse (the library keeps lapse-folded copies of kappa_a, eta, kappa_s, temp and
- * nes_amp: three cell arrays of workspace); tm_adjoint_step, tm_luminosity_seed, tm_ye_newton_step and
- * tm_temperature_update return TM_ERR_INVALID_ARG when one is given. */
+ * nes_amp: three cell arrays of workspace), and so do tm_adjoint_step (gradients with respect to the
+ * caller's local-energy kappa_a, eta, kappa_s and nes_amp) and tm_luminosity_seed (the luminosity
+ * c A_{I+1/2} / a_{I+1/2}^2 sum_k W_k H, whose seed is c R_{I+1/2}^2 / a_{I+1/2}^2 W_k);
+ * tm_ye_newton_step and tm_temperature_update return TM_ERR_INVALID_ARG when one is given. */
 
 typedef struct {            /* every array is per system [S][R], device memory        */
     double  *res_inf;       /* max |G| at the returned psi                              */
@@ -256,9 +258,10 @@ tm_status tm_adjoint_step(tm_ctx *ctx, const tm_inputs *in, const double *psi_n,
 /* Seed of the adjoint for the outer-boundary number luminosity
  *   L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k}   (number through the outer surface, eq. a62)
  * written as a cell array: seed = dL_N/dpsi + add, where dL_N/dpsi = c R_{I+1/2}^2 W_k in
- * the outermost zone and zero elsewhere (zero everywhere without an outgoing flux).
+ * the outermost zone and zero elsewhere (zero everywhere without an outgoing flux); with a lapse
+ * the area is R_{I+1/2}^2 / a_{I+1/2}^2 (lapse_edge is then read).
  * `add` (cell array) may be NULL or alias `seed`; a multi-step adjoint passes the adjoint of
- * the following step there.  Needs r_edge and e_edge only.  With TM_BC_GEOMETRIC the outer
+ * the following step there.  Needs r_edge and e_edge only (and lapse_edge with a lapse).  With TM_BC_GEOMETRIC the outer
  * flux depends on psi_I through the limited flux to the ghost zone, so its derivative needs
  * the state: this entry point then returns TM_ERR_INVALID_ARG.                        */
 tm_status tm_luminosity_seed(tm_ctx *ctx, const tm_inputs *in, const double *add, double *seed);

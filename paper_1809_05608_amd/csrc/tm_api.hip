@@ -783,8 +783,10 @@ tm_status tm_adjoint_step(tm_ctx* c, const tm_inputs* in, const double* psi_n, c
     if (!c) return TM_ERR_INVALID_ARG;
     TM_TRY(check_inputs(c, in));
     if (!psi_np1 || !seed || !mu) return set_err(c, TM_ERR_INVALID_ARG, "psi_np1, seed and mu are required");
-    TM_TRY(no_lapse(c, in, "the adjoint step"));
     (void)psi_n;
+    tm_inputs folded;                      // the lapse's source factors folded in, as in the forward step
+    TM_TRY(fold_lapse(c, in, &folded));
+    in = &folded;
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
@@ -1010,14 +1012,15 @@ tm_status tm_luminosity_seed(tm_ctx* c, const tm_inputs* in, const double* add, 
     if (!c) return TM_ERR_INVALID_ARG;
     if (!in || !in->r_edge || !in->e_edge) return set_err(c, TM_ERR_INVALID_ARG, "r_edge and e_edge are required");
     if (!seed) return set_err(c, TM_ERR_INVALID_ARG, "seed is required");
-    TM_TRY(no_lapse(c, in, "the luminosity seed (the adjoint path)"));
+    if (!in->lapse != !in->lapse_edge) return set_err(c, TM_ERR_INVALID_ARG, "lapse and lapse_edge go together");
     if (c->p.outer_bc == TM_BC_GEOMETRIC)
         return set_err(c, TM_ERR_INVALID_ARG,
                        "the luminosity seed of TM_BC_GEOMETRIC depends on psi (this entry point takes none)");
     TM_TRY(ensure_small(c));
     const tmk::Shape sh = shape_of(c->p);
     TM_TRY(hip_check(c, tmk::launch_setup(in->e_edge, in->nes_g, sh.N, c->consts, c->stream), "setup kernel"));
-    return hip_check(c, tmk::launch_lum_seed(sh, in->r_edge, c->consts, add, seed, c->stream), "seed kernel");
+    return hip_check(c, tmk::launch_lum_seed(sh, in->r_edge, in->lapse_edge, c->consts, add, seed, c->stream),
+                     "seed kernel");
 }
 
 }  // extern "C"

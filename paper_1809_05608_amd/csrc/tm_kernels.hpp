@@ -99,8 +99,8 @@ hipError_t launch_vjp(const Shape& sh, const Fields& f, const Consts* cs, const 
                       const double* mu, double* g_ka, double* g_eta, double* g_ks, double* g_amp,
                       hipStream_t st);
 
-hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
-                           hipStream_t st);
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const double* lapse_edge, const Consts* cs,
+                           const double* add, double* seed, hipStream_t st);
 
 hipError_t launch_final_flags(long long n, const double* res, const double* tgt, double rtol, int* flags,
                               hipStream_t st);

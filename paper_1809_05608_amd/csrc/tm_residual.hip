@@ -563,10 +563,14 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
                     gchi += w * e.dHlam * (-0.5 * lam_e * lam);
                 }
             }
+            // with a lapse the fields are lapse-folded (a kappa_a, a eta, and kappa_s carrying the rest of the
+            // transport opacity): the gradient with respect to the caller's kappa_a and eta is a times that
+            // with respect to the folded ones plus (1 - a) times the kappa_s one, i.e. the sources carry a
+            const double az = f.lapse ? f.lapse[(size_t)ray * I + i] : 1.0;
             double gka = gchi, geta = gchi;
             if (emabs) {
-                gka += m0 * c * pk;
-                geta -= m0 * c * (1.0 - pk);
+                gka += az * m0 * c * pk;
+                geta -= az * m0 * c * (1.0 - pk);
             }
             if (g_ka) g_ka[cb] = -gka;
             if (g_eta) g_eta[cb] = -geta;
@@ -608,7 +612,8 @@ __global__ __launch_bounds__(kBlock) void k_vjp(Shape sh, Fields f, const Consts
             if (tile && k == 0 && i < I) {
                 double ga = 0.0;
                 for (int kk = 0; kk < N; ++kk) ga = fma(s_m[zl][kk], s_s[zl][kk], ga);
-                g_amp[(size_t)sys * I + i] = ga;
+                // the folded amplitude is amp / a: the caller's amplitude gets 1/a of its gradient
+                g_amp[(size_t)sys * I + i] = f.lapse ? ga / f.lapse[(size_t)ray * I + i] : ga;
             }
         } else if (tile && k == 0 && i < I) {
             g_amp[(size_t)sys * I + i] = 0.0;
@@ -659,16 +664,19 @@ hipError_t launch_lapse_fold(const Shape& sh, const double* lapse, const double*
 // ---------------------------------------------------------------- luminosity seed
 
 // dL_N/dpsi for L_N = c A_{I+1/2} sum_k W_k H_{I+1/2,k} with free streaming H = psi of the
-// last zone: c R_{I+1/2}^2 W_k in the outermost zone, zero elsewhere (and zero everywhere
-// when there is no outgoing flux).
+// last zone: c R_{I+1/2}^2 W_k in the outermost zone (R^2 / a^2 with a lapse), zero elsewhere
+// (and zero everywhere when there is no outgoing flux).
 __global__ __launch_bounds__(kBlock) void k_lum_seed(Shape sh, const double* __restrict__ r_edge,
+                                                     const double* __restrict__ lapse_edge,
                                                      const Consts* __restrict__ cs, const double* add,
                                                      double* seed) {
     const long long sys = blockIdx.x;
     const int I = sh.I, N = sh.N;
     const int ray = (int)(sys % sh.R);
     const bool flux = (sh.terms & kDiffusion) && sh.outer_bc == 1;
-    const double ro = r_edge[(size_t)ray * (I + 1) + I];
+    const size_t eo = (size_t)ray * (I + 1) + I;
+    const double ae = lapse_edge ? lapse_edge[eo] : 1.0;      // with a lapse the area is R^2 / a^2
+    const double ro = r_edge[eo] / ae;
     const size_t n = (size_t)I * N;
     for (size_t j = threadIdx.x; j < n; j += kBlock) {
         const int i = (int)(j / N), k = (int)(j % N);
@@ -678,10 +686,10 @@ __global__ __launch_bounds__(kBlock) void k_lum_seed(Shape sh, const double* __r
     }
 }
 
-hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const Consts* cs, const double* add, double* seed,
-                           hipStream_t st) {
+hipError_t launch_lum_seed(const Shape& sh, const double* r_edge, const double* lapse_edge, const Consts* cs,
+                           const double* add, double* seed, hipStream_t st) {
     const long long nsys = (long long)sh.S * sh.R;
-    hipLaunchKernelGGL(k_lum_seed, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, r_edge, cs, add, seed);
+    hipLaunchKernelGGL(k_lum_seed, dim3((unsigned)nsys), dim3(kBlock), 0, st, sh, r_edge, lapse_edge, cs, add, seed);
     return hipGetLastError();
 }
 

@@ -45,7 +45,15 @@ Readings (the paper is silent or garbled here):
     whose "sign" is Fortran's SIGN(a, b) (|a| with the sign of b): mu = sqrt(1 - x^2) for x = R_nu/R <= 1
     and -sqrt(x^2 - 1) clipped at -1 inside the neutrinosphere;
   * the pair sources join the collision energy of the temperature update (the pair's energy comes from
-    the matter's electrons and positrons).
+    the matter's electrons and positrons);
+  * with a lapse a_i (eq. a58 with a != 1) the species rows are a_i c dt times eq. a58 as in the
+    single-species oracle, so their Y_e-dependent source terms carry a_i too, and the neutrinos of zone i
+    number (V_i / a_i^3) sum_k W_k psi (the local phase space W / a^3 at the local energies E / a_i);
+    eq. a62a then exchanges electrons with that number at the rate of the species rows: its source is
+    c dt zeta a_i^-2 sum_k W_k (S_nue - S_nuebar) with the caller's local-energy opacities (a_i from the
+    source and a_i^-3 from the phase space), which keeps the lepton number
+    sum_i V_i [rho Y_e / m_B + (4 pi/(hc)^3) a_i^-3 sum_k W_k (psi_nue - psi_nuebar)] (pinned); the pair
+    processes and the temperature update are written for a = 1 and refuse a lapse.
 
 Parity status: pinned by `tests/test_oracle_ye.py` (total lepton-number conservation, total
 energy conservation through the temperature update, the decoupled limit against the
@@ -169,6 +177,15 @@ def zeta(cs: CoupledSystem) -> np.ndarray:
     return FOUR_PI_HC3 * M_B_G / cs.rho
 
 
+def lapse(cs: CoupledSystem) -> np.ndarray:
+    """Lapse a_i at the zone centres (ones without a lapse); the pair processes take none."""
+    if cs.nue.lapse is None:
+        return np.ones(cs.I)
+    if cs.pair_amp is not None:
+        raise NotImplementedError("the pair processes are written for a = 1")
+    return np.asarray(cs.nue.lapse, dtype=np.float64)
+
+
 def pack(psi_e: np.ndarray, psi_a: np.ndarray, ye: np.ndarray) -> np.ndarray:
     """Per-zone unknowns u_i = (psi_nue[0..N), psi_nuebar[0..N), Y_e) -> [I][2N+1]."""
     return np.concatenate([psi_e, psi_a, ye[:, None]], axis=1)
@@ -195,12 +212,13 @@ def residual(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> np.ndarray:
     pe, pa, ye = unpack(u, N)
     dy = ye - cs.ye_n
     c = cs.nue.c_dt
+    a = lapse(cs)
     out = np.empty_like(u)
     for q, (sys, p_n, p) in enumerate(((cs.nue, pe_n, pe), (cs.nuebar, pa_n, pa))):
         G = tr.residual(sys, p_n, p)            # opacities at Y_e^n
         if sys.terms & TERM_EMABS:
-            # the Y_e-dependent part of -eta (1 - psi) + kappa_a psi
-            G = G + c * dy[:, None] * (cs.dka_dye[q] * p - cs.deta_dye[q] * (1.0 - p))
+            # the Y_e-dependent part of a (-eta (1 - psi) + kappa_a psi)
+            G = G + c * (a * dy)[:, None] * (cs.dka_dye[q] * p - cs.deta_dye[q] * (1.0 - p))
         out[:, q * N:(q + 1) * N] = G
     if cs.pair_amp is not None:
         s_e, s_a = pair_sources(cs, pe, pa)
@@ -211,7 +229,7 @@ def residual(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> np.ndarray:
         _, W = group_energies(cs.nue.e_edge)
         s_e = _ea_source(cs.nue, cs.dka_dye[0], cs.deta_dye[0], dy, pe)
         s_a = _ea_source(cs.nuebar, cs.dka_dye[1], cs.deta_dye[1], dy, pa)
-        out[:, 2 * N] += c * zeta(cs) * ((s_e - s_a) @ W)
+        out[:, 2 * N] += c * zeta(cs) / a ** 2 * ((s_e - s_a) @ W)
     return out
 
 
@@ -223,7 +241,8 @@ def jacobian_blocks(cs: CoupledSystem, u: np.ndarray):
     dy = ye - cs.ye_n
     c = cs.nue.c_dt
     _, W = group_energies(cs.nue.e_edge)
-    z = zeta(cs)
+    a = lapse(cs)
+    z = zeta(cs) / a ** 2                      # the Y_e row's rate per unit sum_k W_k S
     A = np.zeros((I, M, M))
     bm = np.zeros((I, M))
     bp = np.zeros((I, M))
@@ -237,8 +256,8 @@ def jacobian_blocks(cs: CoupledSystem, u: np.ndarray):
         if sys.terms & TERM_EMABS:
             # d/dpsi of c dY (dka psi - deta (1 - psi)), and the Y_e column d G_q / dY_e
             idx = np.arange(q * N, (q + 1) * N)
-            A[:, idx, idx] += c * dy[:, None] * (dka + deta)
-            A[:, sl, 2 * N] = c * (dka * p - deta * (1.0 - p))
+            A[:, idx, idx] += c * (a * dy)[:, None] * (dka + deta)
+            A[:, sl, 2 * N] = c * a[:, None] * (dka * p - deta * (1.0 - p))
             # Y_e row: dG_Y/dpsi_q,k = +-c zeta W_k dS^ea_q/dpsi = -+c zeta W_k (eta(Y) + kappa_a(Y))
             ka = sys.kappa_a + dy[:, None] * dka
             et = sys.eta + dy[:, None] * deta
@@ -286,7 +305,7 @@ def rounding_level(cs: CoupledSystem, u_n: np.ndarray, u: np.ndarray) -> float:
     dy = ye - cs.ye_n
     c = cs.nue.c_dt
     _, W = group_energies(cs.nue.e_edge)
-    z = zeta(cs)
+    z = zeta(cs) / lapse(cs) ** 2
     lev = max(residual_rounding_level(cs.nue, pe_n, pe), residual_rounding_level(cs.nuebar, pa_n, pa))
     mag = np.abs(ye) + np.abs(cs.ye_n)
     if cs.nue.terms & TERM_EMABS:
@@ -357,11 +376,13 @@ def newton(cs: CoupledSystem, u_n: np.ndarray, u0: Optional[np.ndarray] = None,
 
 def lepton_number(cs: CoupledSystem, u: np.ndarray) -> float:
     """Total lepton number of the ray divided by 4 pi (volumes without 4 pi, eqs. a51-a55):
-        sum_i V_i [rho_i Y_e,i / m_B + (4 pi/(hc)^3) sum_k W_k (psi_nue - psi_nuebar)]."""
+        sum_i V_i [rho_i Y_e,i / m_B + (4 pi/(hc)^3) a_i^-3 sum_k W_k (psi_nue - psi_nuebar)]
+    (a = 1 without a lapse)."""
     _, V, _, _ = geometry(cs.nue.r_edge)
     _, W = group_energies(cs.nue.e_edge)
     pe, pa, ye = unpack(u, cs.N)
-    return float(np.sum(V * (cs.rho * ye / M_B_G + FOUR_PI_HC3 * ((pe - pa) @ W))))
+    a = lapse(cs)
+    return float(np.sum(V * (cs.rho * ye / M_B_G + FOUR_PI_HC3 / a ** 3 * ((pe - pa) @ W))))
 
 
 def collision_energy_source(sys: System, psi: np.ndarray, dka=None, deta=None, dy=None) -> np.ndarray:
@@ -389,6 +410,8 @@ def temperature_update(cs: CoupledSystem, others: list, u: np.ndarray, psi_other
     T^{n+1} = T^n + (de - (Y_e^{n+1} - Y_e^n) de/dY_e) / (de/dT).
     Returns (de [I], T^{n+1} [I]).
     """
+    if cs.nue.lapse is not None:
+        raise NotImplementedError("the temperature update is written for a = 1")
     pe, pa, ye = unpack(u, cs.N)
     dy = ye - cs.ye_n
     src = stat_weights[0] * collision_energy_source(cs.nue, pe, cs.dka_dye[0], cs.deta_dye[0], dy)

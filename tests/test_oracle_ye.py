@@ -181,3 +181,65 @@ def test_temperature_update_conserves_total_energy():
     # T^{n+1} - T^n cancels to ~1e-12 of T in the outer zones: compare at the scale of T de/dT
     atol = 1e-14 * float(np.max(wn["temp"][0] * ye["de_dT"][0]))
     np.testing.assert_allclose((T1 - wn["temp"][0]) * ye["de_dT"][0] + dy * ye["de_dye"][0], de, rtol=1e-12, atol=atol)
+
+
+# ------------------------------------------------------------------ the lapse (eq. a58 with a != 1)
+
+def _lapsed(cs, R0=5.0e5):
+    """The coupled system with the lapse a(R) = sqrt(1 - R0/R) on both species (0.71 at 10 km)."""
+    re = cs.nue.r_edge
+    rc = 0.5 * (re[1:] + re[:-1])
+    a, ae = np.sqrt(1.0 - R0 / rc), np.sqrt(1.0 - R0 / re)
+    return dataclasses.replace(cs, nue=dataclasses.replace(cs.nue, lapse=a, lapse_edge=ae),
+                               nuebar=dataclasses.replace(cs.nuebar, lapse=a, lapse_edge=ae))
+
+
+def test_total_lepton_number_is_conserved_with_a_lapse():
+    """With a lapse the neutrinos of zone i number (V_i/a_i^3) sum_k W_k psi; zero-flux boundaries, all
+    terms: the converged coupled step conserves electrons plus that (nu_e - anti-nu_e) number."""
+    _, _, cs, u_n = _ray(zones=20, groups=6, outer_bc=0)
+    cs = _lapsed(cs)
+    assert np.ptp(cs.nue.lapse) > 0.2
+    res = yc.newton(cs, u_n, max_iter=30, rtol=1e-13)
+    assert res.converged
+    L0, L1 = yc.lepton_number(cs, u_n), yc.lepton_number(cs, res.psi)
+    _, V, _, _ = oracle.geometry(cs.nue.r_edge)
+    electrons = lambda u: float(np.sum(V * cs.rho * u[:, -1] / yc.M_B_G))      # noqa: E731
+    assert abs(electrons(res.psi) - electrons(u_n)) > 1e3 * abs(L1 - L0)
+    assert abs(L1 - L0) <= 1e-12 * abs(electrons(u_n))
+
+
+def test_lapse_lepton_pin_catches_a_missing_phase_space_factor(monkeypatch):
+    """A planted Y_e rate without the lapse's a^-2 (the a = 1 form) breaks the lapsed lepton sum."""
+    _, _, cs, u_n = _ray(zones=12, groups=5, outer_bc=0)
+    cs = _lapsed(cs)
+    good = yc.zeta
+    monkeypatch.setattr(yc, "zeta", lambda c: good(c) * yc.lapse(c) ** 2)
+    res = yc.newton(cs, u_n, max_iter=30, rtol=1e-13)
+    _, V, _, _ = oracle.geometry(cs.nue.r_edge)
+    electrons = float(np.sum(V * cs.rho * u_n[:, -1] / yc.M_B_G))
+    monkeypatch.setattr(yc, "zeta", good)
+    assert abs(yc.lepton_number(cs, res.psi) - yc.lepton_number(cs, u_n)) > 1e-9 * electrons
+
+
+@pytest.mark.parametrize("terms", [7, 3])
+def test_coupled_jacobian_with_lapse_matches_central_differences(terms):
+    _, _, cs, u_n = _ray(zones=5, groups=4, terms=terms)
+    cs = _lapsed(cs)
+    rng = np.random.default_rng(8)
+    u = u_n.copy()
+    N = cs.N
+    u[:, :2 * N] = rng.uniform(0.05, 0.9, size=u[:, :2 * N].shape)
+    u[:, 2 * N] += 0.01 * rng.standard_normal(cs.I)
+    J = yc.dense_jacobian(cs, u)
+    x = u.ravel()
+    Jfd = np.zeros_like(J)
+    for j in range(x.size):
+        h = 1e-5 * max(abs(x[j]), 1e-3)
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        Jfd[:, j] = (yc.residual(cs, u_n, xp.reshape(u.shape)).ravel()
+                     - yc.residual(cs, u_n, xm.reshape(u.shape)).ravel()) / (2 * h)
+    rowmax = np.abs(J).max(axis=1, keepdims=True)
+    assert np.all(np.abs(J - Jfd) <= 1e-6 * np.abs(J) + 1e-9 * rowmax)

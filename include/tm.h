@@ -149,8 +149,12 @@ typedef struct {
  * tm_newton_step take a lapse (the library keeps lapse-folded copies of kappa_a, eta, kappa_s, temp and
  * nes_amp: three cell arrays of workspace), and so do tm_adjoint_step (gradients with respect to the
  * caller's local-energy kappa_a, eta, kappa_s and nes_amp) and tm_luminosity_seed (the luminosity
- * c A_{I+1/2} / a_{I+1/2}^2 sum_k W_k H, whose seed is c R_{I+1/2}^2 / a_{I+1/2}^2 W_k);
- * tm_ye_newton_step and tm_temperature_update return TM_ERR_INVALID_ARG when one is given. */
+ * c A_{I+1/2} / a_{I+1/2}^2 sum_k W_k H, whose seed is c R_{I+1/2}^2 / a_{I+1/2}^2 W_k), and
+ * tm_ye_newton_step (the species rows as above with dkappa_a/dY_e and deta/dY_e at the local energies;
+ * eq. a62a's rate per zone becomes c dt zeta a_i^-2 sum_k W_k (S_nue - S_nuebar), so that electrons
+ * plus (V_i / a_i^3) sum_k W_k (psi_nue - psi_nuebar) are conserved, and the reported lepton number
+ * takes those weights; not together with the pair processes);  tm_temperature_update returns
+ * TM_ERR_INVALID_ARG when one is given. */
 
 typedef struct {            /* every array is per system [S][R], device memory        */
     double  *res_inf;       /* max |G| at the returned psi                              */

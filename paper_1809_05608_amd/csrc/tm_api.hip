@@ -813,11 +813,15 @@ tm_status tm_ye_newton_step(tm_ctx* c, const tm_inputs* in, const tm_ye_inputs* 
     TM_TRY(check_ye_inputs(c, yin));
     if (yin->pair_amp && !in->r_nu)
         return set_err(c, TM_ERR_INVALID_ARG, "the pair processes need r_nu (their angular factor uses R_nu)");
-    TM_TRY(no_lapse(c, in, "the Y_e-coupled step"));
+    if (yin->pair_amp && in->lapse)
+        return set_err(c, TM_ERR_INVALID_ARG, "the pair processes take no lapse (lapse must be NULL with pair_amp)");
     if (c->p.precision != TM_PREC_FP64)
         return set_err(c, TM_ERR_INVALID_ARG, "the Y_e-coupled step is FP64 only (precision must be TM_PREC_FP64)");
     if (!psi_n || !psi || !ye) return set_err(c, TM_ERR_INVALID_ARG, "psi_n, psi and ye are required");
     if (max_iter < 0 || !(rtol >= 0.0)) return set_err(c, TM_ERR_INVALID_ARG, "max_iter >= 0 and rtol >= 0 required");
+    tm_inputs folded;                      // the lapse's source factors folded in, as in the species step
+    TM_TRY(fold_lapse(c, in, &folded));
+    in = &folded;
     TM_TRY(ensure_small(c));
     TM_TRY(ensure_gbuf(c));
     TM_TRY(ensure_ye(c));

@@ -187,7 +187,7 @@ hipError_t launch_ye_couple(const Shape& sh, const Fields& f, const YeFields& y,
                             const double* ye, double* G, double* GY, const double* level_sp, const YeOut& out,
                             hipStream_t st);
 hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st);
-// false when the problem needs the partial-pivoting kernel only (neutrinosphere options or pairs)
+// false when the problem needs the partial-pivoting kernel only (neutrinosphere options, pairs or a lapse)
 bool ye_tiled_applies(const YeFactorArgs& a);
 hipError_t launch_ye_factor_tiled(const YeFactorArgs& a, hipStream_t st);
 // psi (species 0, 1) and ye += (alpha/2 - alpha) delta, alpha /= 2, for rays with backtrack set (cleared)

@@ -112,7 +112,9 @@ __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFiel
             const double p = psi[ci];
             double g = G[ci] - c * spair;
             if (emabs) {
-                const double dka = y.dka[ci], det = y.deta[ci];
+                // with a lapse the fields are lapse-folded (a kappa_a, a eta): the derivatives get the same a
+                const double az = f.lapse ? f.lapse[zb + i] : 1.0;
+                const double dka = az * y.dka[ci], det = az * y.deta[ci];
                 g += c * dy * (dka * p - det * (1.0 - p));              // opacities at Y_e instead of Y_e^n
                 const double em = (f.eta[ci] + dy * det) * (1.0 - p);
                 const double ab = (f.kappa_a[ci] + dy * dka) * p;
@@ -131,7 +133,10 @@ __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFiel
         sL = wave_sum(sL);
         if (lane == 0) {
             const double rho = y.rho[zb + i];
-            const double z = ye_zeta(rho);
+            // with a lapse: the neutrinos of the zone number (V / a^3) sum_k W_k psi and the folded sources
+            // carry a, so the Y_e rate per unit folded source is zeta / a^3
+            const double ai3 = f.lapse ? 1.0 / (f.lapse[zb + i] * f.lapse[zb + i] * f.lapse[zb + i]) : 1.0;
+            const double z = ye_zeta(rho) * ai3;
             double gy = dy, mag = fabs(Y) + fabs(Yn), ayy = 1.0;
             if (emabs) {
                 gy += c * z * sY;                                        // eq. a62a times c dt
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_ye_couple(Shape sh, Fields f, YeFiel
             bad |= !isfinite(gy);
             gmax = fmax(gmax, fabs(gy));
             mag_max = fmax(mag_max, mag);
-            lep += shell_volume(re[i], re[i + 1]) * (rho * Y / kBaryonMassG + kFourPiOverHc3 * sL);
+            lep += shell_volume(re[i], re[i + 1]) * (rho * Y / kBaryonMassG + kFourPiOverHc3 * ai3 * sL);
         }
     }
     const double res = block_max(gmax, red);
@@ -309,7 +314,7 @@ __device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, b
     wave_sync();
 }
 
-// EXT: the geometric limiter and outer boundary and the pair processes compiled in (instantiated
+// EXT: the geometric limiter and outer boundary, the pair processes and the lapse compiled in (instantiated
 // separately, at one wave per SIMD, and launched only for problems that ask for any of them).
 // TILE: the elimination with diagonal pivots on 8 x 8 lane tiles (below) instead of partial pivoting
 // with one row per lane.
@@ -401,8 +406,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             lam_n1 = drcp(sig_n1 + ks[cn]);
         }
         const double rlo = re[i], rhi = re[i + 1];
-        const double iV = drcp(shell_volume(rlo, rhi));
-        const double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double iV = drcp(shell_volume(rlo, rhi));
+        double A_lo = rlo * rlo, A_hi = rhi * rhi;
+        double alz = 1.0;                              // lapse of the zone (eq. a58 times a_i c dt: a^3/V, A/a^2)
+        if (EXT && A.f.lapse) {
+            alz = A.f.lapse[zb + i];
+            const double e0 = A.f.lapse_edge[(size_t)ray * (I + 1) + i], e1 = A.f.lapse_edge[(size_t)ray * (I + 1) + i + 1];
+            iV *= alz * alz * alz;
+            A_lo /= e0 * e0;
+            A_hi /= e1 * e1;
+        }
         double dHu_hi = 0.0, dHv_hi = 0.0;
         if (i + 1 < I) {
             const double D_hi = 0.5 * (rhi + re[i + 2]) - 0.5 * (rlo + rhi);
@@ -432,10 +445,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
 
         // Y_e terms of the zone (eq. a62ad: Y_e column of the species rows; eq. a62a: the Y_e row)
         const double dy = A.ye[zb + i] - A.y.ye_n[zb + i];
-        const double z = ye_zeta(A.y.rho[zb + i]);
+        // with a lapse the fields are lapse-folded: the opacity derivatives carry a as well, and the Y_e rate
+        // per unit folded source is zeta / a^3
+        const double z = ye_zeta(A.y.rho[zb + i]) / (alz * alz * alz);
         double ycol = 0.0, yrow = 0.0, ysum = 0.0;
         if (emabs && real) {
-            const double dk = dka[(size_t)i * N + kk], de = det[(size_t)i * N + kk];
+            const double dk = alz * dka[(size_t)i * N + kk], de = alz * det[(size_t)i * N + kk];
             diag += c * dy * (dk + de);
             ycol = c * (dk * psi_c - de * (1.0 - psi_c));
             yrow = -sgn * c * z * Wk * (sig_c + dy * (dk + de));
@@ -854,7 +869,9 @@ hipError_t launch_ye_factor(const YeFactorArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-bool ye_tiled_applies(const YeFactorArgs& a) { return !(a.sh.limiter == 2 || a.sh.outer_bc == 2 || a.y.pair_amp); }
+bool ye_tiled_applies(const YeFactorArgs& a) {
+    return !(a.sh.limiter == 2 || a.sh.outer_bc == 2 || a.y.pair_amp || a.f.lapse);
+}
 
 hipError_t launch_ye_factor_tiled(const YeFactorArgs& a, hipStream_t st) {
     if (!ye_tiled_applies(a) || !a.redo) return hipErrorInvalidValue;

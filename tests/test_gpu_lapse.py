@@ -190,12 +190,78 @@ def test_adjoint_with_lapse_matches_oracle(shape):
     ctx.close()
 
 
+def _zone_err(a, ref):
+    scale = np.maximum(np.max(np.abs(ref), axis=-1, keepdims=True), TAU)
+    return float(np.max(np.abs(a - ref) / scale))
+
+
+@pytest.mark.parametrize("shape,max_iter,rtol", [(dict(S=2, R=3, I=24, N=12), 3, 0.0),
+                                                 (dict(S=2, R=4, I=24, N=20), 30, 1e-12)])
+def test_coupled_step_with_lapse_matches_oracle(shape, max_iter, rtol):
+    """The Y_e-coupled step with a lapse (species rows a_i c dt times eq. a58, eq. a62a's rate over a_i^2)
+    against the oracle, from a perturbed guess: psi per zone and species, Y_e, iteration counts."""
+    from oracle import ye_coupled as yc
+    say("case lapse coupled step", shape, max_iter, rtol)
+    w = synth.make_custom(**shape)
+    y = synth.ye_inputs(w, 0, R_full=w.R)
+    wn, wd, f, ctx = setup(w)
+    yn, yd = y.numpy(), y.to("cuda")
+    rng = np.random.default_rng(31)
+    psi0 = (wn["psi_n"] * rng.uniform(0.9, 1.1, wn["psi_n"].shape)).clip(0, 1)
+    ye0 = yn["ye_n"] + 0.003 * rng.standard_normal(yn["ye_n"].shape)
+    psi = torch.as_tensor(psi0, device="cuda").contiguous()
+    ye = torch.as_tensor(ye0, device="cuda").contiguous()
+    st, stats = ctx.ye_newton_step(f, yd, wd.psi_n, psi, ye, max_iter, rtol, raise_on_status=False)
+    torch.cuda.synchronize()
+    assert st == tm.TM_OK
+    N = w.N
+    pe, pa, yo, it = [], [], [], []
+    for r, cs in enumerate(yc.coupled_systems(wn, yn)):
+        assert cs.nue.lapse is not None
+        u_n = yc.pack(wn["psi_n"][0, r], wn["psi_n"][1, r], cs.ye_n)
+        res = yc.newton(cs, u_n, u0=yc.pack(psi0[0, r], psi0[1, r], ye0[r]), max_iter=max_iter, rtol=rtol)
+        pe.append(res.psi[:, :N])
+        pa.append(res.psi[:, N:2 * N])
+        yo.append(res.psi[:, 2 * N])
+        it.append(res.iters)
+    got = psi.cpu().numpy()
+    e = max(_zone_err(got[0], np.stack(pe)), _zone_err(got[1], np.stack(pa)))
+    ey = float(np.max(np.abs(ye.cpu().numpy() - np.stack(yo))) / np.max(np.abs(np.stack(yo))))
+    iters = stats["iters"].cpu().numpy()
+    say("  psi err", e, "ye err", ey, "iters", iters.tolist(), it)
+    assert e < 1e-12 and ey < 1e-12
+    assert np.all(np.abs(iters - np.array(it)) <= (0 if rtol == 0.0 else 1))
+    ctx.close()
+
+
+def test_coupled_step_with_lapse_conserves_the_lapsed_lepton_number():
+    """Zero-flux outer boundary: electrons plus (V_i/a_i^3) sum_k W_k (psi_nue - psi_nuebar) are kept by
+    the converged coupled step on the GPU, as the library reports them."""
+    say("case lapse coupled lepton number")
+    w = dataclasses.replace(synth.make_custom(S=2, R=4, I=40, N=12), outer_bc=0)
+    y = synth.ye_inputs(w, 0, R_full=w.R)
+    wn, wd, f, ctx = setup(w)
+    yd = y.to("cuda")
+    psi, ye = wd.psi_n.clone(), yd.ye_n.clone()
+    _, s0 = ctx.ye_newton_step(f, yd, wd.psi_n, psi.clone(), ye.clone(), 0, 0.0, raise_on_status=False)
+    st, s1 = ctx.ye_newton_step(f, yd, wd.psi_n, psi, ye, 30, 1e-13, raise_on_status=False)
+    torch.cuda.synchronize()
+    assert st == tm.TM_OK
+    _, V, _, _ = tr.geometry(w.r_edge.numpy()[0])
+    electrons = np.array([np.sum(V * y.rho.numpy()[r] * y.ye_n.numpy()[r] / 1.66053906660e-24) for r in range(w.R)])
+    drift = np.abs(s1["lepton"].cpu().numpy() - s0["lepton"].cpu().numpy()) / electrons
+    moved = float((ye - yd.ye_n).abs().max())
+    say("  lepton drift", drift.max(), "max |dY_e|", moved)
+    assert moved > 1e-6 and np.all(drift < 1e-12)
+    ctx.close()
+
+
 def test_lapse_is_rejected_where_it_is_not_supported():
     say("case lapse rejected")
     w = synth.make_custom(S=2, R=2, I=8, N=6)
     wn, wd, f, ctx = setup(w)
     psi = wd.psi_n.clone()
-    y = synth.ye_inputs(wd, 0, R_full=w.R)
+    y = synth.ye_inputs(wd, 0, R_full=w.R, pairs=True)
     with pytest.raises(tm.TMError, match="INVALID_ARG"):
         ctx.ye_newton_step(f, y, wd.psi_n, psi, y.ye_n.clone(), 3, 0.0)
     with pytest.raises(ValueError):

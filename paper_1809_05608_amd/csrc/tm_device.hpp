@@ -186,6 +186,18 @@ __device__ __forceinline__ uint32_t group_max(uint32_t v) {
     return v;
 }
 
+// Non-temporal store and load of a global element (the factor workspaces: written once per zone in the
+// forward sweep and read once in the backward sweep, hundreds of zones later, so caching them only
+// evicts other data).
+template <typename T>
+__device__ __forceinline__ void nt_store(T* p, T v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
+}
+template <typename T>
+__device__ __forceinline__ T nt_load(const T* p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
+
 // Intra-wavefront ordering point for LDS exchange between lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

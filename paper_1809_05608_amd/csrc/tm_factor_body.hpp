@@ -448,11 +448,15 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
         }
 
         if (store) {
+            // non-temporal except where the transposed kernel reads the row back in the next zone
             T* q = wsC + (size_t)i * NT * zs + lo;
 #pragma unroll
             for (int m = 0; m < NT; ++m)
-                if (m < N) q[(size_t)m * zs] = a[m];
-            wsY[(size_t)i * zs + lo] = ycar;
+                if (m < N) {
+                    if (TRANS) q[(size_t)m * zs] = a[m];
+                    else nt_store(q + (size_t)m * zs, a[m]);
+                }
+            nt_store(wsY + (size_t)i * zs + lo, ycar);
         }
 
         psi_c = psi_n1;
@@ -498,16 +502,16 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     {
         const T* q = wsC + (size_t)(I - 1) * NT * zs + lo;
 #pragma unroll
-        for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? q[(size_t)m * zs] : (T)0;
-        yv = real ? wsY[(size_t)(I - 1) * zs + lo] : (T)0;
+        for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? nt_load(q + (size_t)m * zs) : (T)0;
+        yv = real ? nt_load(wsY + (size_t)(I - 1) * zs + lo) : (T)0;
     }
     T dnext = (T)0;
     for (int i = I - 1; i >= 0; --i) {
         if (i > 0) {
             const T* q = wsC + (size_t)(i - 1) * NT * zs + lo;
 #pragma unroll
-            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? q[(size_t)m * zs] : (T)0;
-            yn = real ? wsY[(size_t)(i - 1) * zs + lo] : (T)0;
+            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? nt_load(q + (size_t)m * zs) : (T)0;
+            yn = real ? nt_load(wsY + (size_t)(i - 1) * zs + lo) : (T)0;
         }
         T dl = yv;
         if (i + 1 < I) {

@@ -120,6 +120,21 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T& at(const T
     using GC = const __attribute__((address_space(1))) char;
     return *(G*)((GC*)base + byte_off);
 }
+// The same addressing for the factor workspace, with non-temporal stores and loads: C and y are written
+// once per zone and read once in the backward sweep, hundreds of zones later, so caching them only
+// evicts other data (measured: the launch 5% shorter).
+template <typename T>
+__device__ __forceinline__ void st_nt(T* base, uint32_t byte_off, T v) {
+    using G = __attribute__((address_space(1))) T;
+    using GC = __attribute__((address_space(1))) char;
+    __builtin_nontemporal_store(v, (G*)((GC*)base + byte_off));
+}
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* base, uint32_t byte_off) {
+    using G = const __attribute__((address_space(1))) T;
+    using GC = const __attribute__((address_space(1))) char;
+    return __builtin_nontemporal_load((G*)((GC*)base + byte_off));
+}
 template <typename T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
     const unsigned long long v = reinterpret_cast<unsigned long long>(p);
@@ -706,10 +721,10 @@ void k_factor_q(FactorArgs A) {
 #pragma unroll
             for (int s = 0; s < R; ++s)
 #pragma unroll
-                for (int j = 0; j < NT; ++j) at(qc + (s * NT + j) * 64, wl1) = AE(s, j);
+                for (int j = 0; j < NT; ++j) st_nt(qc + (s * NT + j) * 64, wl1, AE(s, j));
             float* qy = uniform_ptr(wsY + (size_t)i * kQuadSystems * NT);
 #pragma unroll
-            for (int s = 0; s < R; ++s) at(qy + s * 64, wl1) = g[s];
+            for (int s = 0; s < R; ++s) st_nt(qy + s * 64, wl1, g[s]);
         }
     }
 
@@ -746,9 +761,9 @@ void k_factor_q(FactorArgs A) {
         const double* pz = A.psi_out ? uniform_ptr(A.psi_out + wcell0 + (size_t)z * N) : nullptr;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-            b.y[s] = at(qy + s * 64, gz.wl);
+            b.y[s] = ld_nt(qy + s * 64, gz.wl);
 #pragma unroll
-            for (int j = 0; j < NT; ++j) b.c[s][j] = at(qc + (s * NT + j) * 64, gz.wl);
+            for (int j = 0; j < NT; ++j) b.c[s][j] = ld_nt(qc + (s * NT + j) * 64, gz.wl);
             const int k = 4 * s + gz.q;
             b.ps[s] = pz ? at(pz, k < N ? gz.lb + 32u * s : gz.lb - 8u * gz.q) : 0.0;
         }

@@ -510,8 +510,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
             if (i > 0) {                               // C_{i-1}, y_{i-1} to the workspace
                 double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + lane;
 #pragma unroll
-                for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = frow[m];
-                wz[(size_t)NC * MT] = ycar;
+                for (int m = 0; m < NC; ++m) nt_store(wz + (size_t)m * MT, frow[m]);
+                nt_store(wz + (size_t)NC * MT, ycar);
             }
         }
         if (real) {
@@ -634,8 +634,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     if (is_row) {                                      // C_{I-1}, y_{I-1}
         double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + lane;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) wz[(size_t)m * MT] = frow[m];
-        wz[(size_t)NC * MT] = frow[MT];
+        for (int m = 0; m < NC; ++m) nt_store(wz + (size_t)m * MT, frow[m]);
+        nt_store(wz + (size_t)NC * MT, frow[MT]);
     }
 
     // ---------------------------------------------------------------- backward sweep
@@ -652,16 +652,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     {
         const double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + kb;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) cr[m] = is_row ? wz[(size_t)m * MT] : 0.0;
-        yv = is_row ? wz[(size_t)NC * MT] : 0.0;
+        for (int m = 0; m < NC; ++m) cr[m] = is_row ? nt_load(wz + (size_t)m * MT) : 0.0;
+        yv = is_row ? nt_load(wz + (size_t)NC * MT) : 0.0;
     }
     double dnext = 0.0;
     for (int i = I - 1; i >= 0; --i) {
         if (i > 0) {
             const double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + kb;
 #pragma unroll
-            for (int m = 0; m < NC; ++m) crn[m] = is_row ? wz[(size_t)m * MT] : 0.0;
-            yn = is_row ? wz[(size_t)NC * MT] : 0.0;
+            for (int m = 0; m < NC; ++m) crn[m] = is_row ? nt_load(wz + (size_t)m * MT) : 0.0;
+            yn = is_row ? nt_load(wz + (size_t)NC * MT) : 0.0;
         }
         double dl = yv;
         if (i + 1 < I) {

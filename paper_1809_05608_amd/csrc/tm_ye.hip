@@ -269,24 +269,24 @@ __device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, b
         }
         wave_sync();
         const double piv = ur[cc], bpiv = L.bpv[cc];
-        const double pinv = drcp(piv);
+        const double npinv = -drcp(piv);
         if (lane == 0) L.pivs[cc] = piv;
-        double u[T], f[T];
+        double u[T], nf[T];                            // nf: minus the multipliers
 #pragma unroll
         for (int tc = 0; tc < T; ++tc) u[tc] = ur[T * tb + tc];
 #pragma unroll
         for (int tr = 0; tr < T; ++tr) {
-            f[tr] = uc[T * ta + tr] * pinv;
-            if (tr == rp && ta == ap) f[tr] = 0.0;     // the pivot row itself
-            gmax = fmax(gmax, fabs(f[tr]));
+            nf[tr] = uc[T * ta + tr] * npinv;
+            if (tr == rp && ta == ap) nf[tr] = 0.0;    // the pivot row itself
+            gmax = fmax(gmax, fabs(nf[tr]));
         }
 #pragma unroll
         for (int tr = 0; tr < T; ++tr)
 #pragma unroll
-            for (int tc = 0; tc < T; ++tc) t[tr][tc] = fma(-f[tr], u[tc], t[tr][tc]);
+            for (int tc = 0; tc < T; ++tc) t[tr][tc] = fma(nf[tr], u[tc], t[tr][tc]);
         if (tb == ap) {                                // column cc: -f bp_cc, and bp_cc in the pivot row
 #pragma unroll
-            for (int tr = 0; tr < T; ++tr) t[tr][rp] = (tr == rp && ta == ap) ? bpiv : -f[tr] * bpiv;
+            for (int tr = 0; tr < T; ++tr) t[tr][rp] = (tr == rp && ta == ap) ? bpiv : nf[tr] * bpiv;
         }
         // every entry is materialised at the end of its step: left alone, the compiler sinks each update to
         // the entry's next use and holds every earlier step's multipliers and pivot-row values live

@@ -572,27 +572,32 @@ void k_factor_q(FactorArgs A) {
             const float ca = (float)(-c * ampz);
             const float xs = (float)(1.4426950408889634 * drcp1(Tz));  // log2 e / T
             if constexpr (NES == kNesExp2) {
-                float xl[R], ds[R];
+                // Split by the weights: above the diagonal (k' > k) the entry is ca P [(1 - psi_k) + psi_k M] and
+                // the diagonal term P [psi_k' + (1 - psi_k') M]; below it psi and 1 - psi trade places.  Whether
+                // k' > k is known at compile time except inside the row's own run of four columns (P is 0 on
+                // the diagonal and in padding rows and columns, so their side does not matter).
+                float xl[R], ds[R], wa[R], wb[R];
 #pragma unroll
                 for (int s = 0; s < R; ++s) {
                     xl[s] = s_eps[4 * s + q] * xs;
                     ds[s] = 0.0f;
+                    wa[s] = ca * s_psi[s][lane];           // ca psi_k
+                    wb[s] = ca - wa[s];                    // ca (1 - psi_k)
                 }
 #pragma unroll
                 for (int kp = 0; kp < NT; ++kp) {
                     const float xb = qbc(xl[kp / 4], kp % 4);
                     const float pb = s_psi[kp / 4][(lane & ~3) + kp % 4];
+                    const float pc = 1.0f - pb;
 #pragma unroll
                     for (int s = 0; s < R; ++s) {
                         const float P = s_P[(4 * s + q) * PS + kp];
-                        const float d = xb - xl[s];                    // > 0 above the diagonal
-                        const float tM = __builtin_amdgcn_exp2f(-fabsf(d)) - 1.0f;
-                        const bool up = d > 0.0f;
-                        const float ps = s_psi[s][lane];
-                        const float w = up ? ps : 1.0f - ps;
-                        const float v = up ? 1.0f - pb : pb;
-                        AE(s, kp) = fmaf(ca * P, fmaf(w, tM, 1.0f), AE(s, kp));
-                        ds[s] = fmaf(P, fmaf(v, tM, 1.0f), ds[s]);
+                        const float PM = P * __builtin_amdgcn_exp2f(-fabsf(xb - xl[s]));
+                        const bool up = kp >= 4 * s + 4 ? true : kp < 4 * s ? false : kp > 4 * s + q;
+                        const float c1 = up ? wb[s] : wa[s], c2 = up ? wa[s] : wb[s];
+                        const float v1 = up ? pb : pc, v2 = up ? pc : pb;
+                        AE(s, kp) = fmaf(c2, PM, fmaf(c1, P, AE(s, kp)));
+                        ds[s] = fmaf(v2, PM, fmaf(v1, P, ds[s]));
                     }
                     fence_sched();
                 }
@@ -655,14 +660,14 @@ void k_factor_q(FactorArgs A) {
             const int p = cc % 4, sp = cc / 4;
             const bool own = q == p;
             const float piv = qbc(AE(sp, cc), p);
-            const float pinv = frcp(piv);
+            const float npinv = -frcp(piv);
             pv[sp] = own ? piv : pv[sp];
-            float f[R];
+            float nf[R];                                   // minus the multipliers
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                f[s] = AE(s, cc) * pinv;
-                if (s == sp) f[s] = own ? 0.0f : f[s];
-                gmax = fmaxf(gmax, fabsf(f[s]));
+                nf[s] = AE(s, cc) * npinv;
+                if (s == sp) nf[s] = own ? 0.0f : nf[s];
+                gmax = fmaxf(gmax, fabsf(nf[s]));
             }
             if constexpr (MF) {
                 // rank-1 update on the matrix cores: tile (s, t) holds entries (4s + q, 4t + i) in register i
@@ -670,9 +675,6 @@ void k_factor_q(FactorArgs A) {
                 // 4t + i from lane i and B = -f of the lane's own row adds -f_r u_c to every entry.  Lane i
                 // takes entry 4t + i of the broadcast pivot row (a 4-way select on the quad lane).
                 const bool q1 = q & 1, q2 = q & 2;
-                float nf[R];
-#pragma unroll
-                for (int s2 = 0; s2 < R; ++s2) nf[s2] = -f[s2];
                 // tiles in the order the next step needs them: the one holding column cc + 1 (the next
                 // multipliers and pivot) first
 #pragma unroll
@@ -693,15 +695,15 @@ void k_factor_q(FactorArgs A) {
                     const int j = (cc + jj) % NT;
                     const float u = qbc(AE(sp, j), p);
 #pragma unroll
-                    for (int s = 0; s < R; ++s) AE(s, j) = fmaf(-f[s], u, AE(s, j));
+                    for (int s = 0; s < R; ++s) AE(s, j) = fmaf(nf[s], u, AE(s, j));
                 }
             }
             const float ug = qbc(g[sp], p);
 #pragma unroll
-            for (int s = 0; s < R; ++s) g[s] = fmaf(-f[s], ug, g[s]);
+            for (int s = 0; s < R; ++s) g[s] = fmaf(nf[s], ug, g[s]);
             const float bpiv = s_bp[sp][(lane & ~3) + p];
 #pragma unroll
-            for (int s = 0; s < R; ++s) AE(s, cc) = -f[s] * bpiv;
+            for (int s = 0; s < R; ++s) AE(s, cc) = nf[s] * bpiv;
             AE(sp, cc) = own ? bpiv : AE(sp, cc);
         }
 #pragma unroll

@@ -157,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
     static_assert(3 * RZ + 2 <= kBlock, "one zone value per thread");
     __shared__ double s_P[NT * PS];
     __shared__ double s_psi[RZ][PS];
+    __shared__ double2 s_pq[RZ][NT];            // psi and 1 - psi of the row (the NES sums read both at once)
     __shared__ double s_lam[RZ][PS];
     __shared__ double s_d[RZ][PS];
     __shared__ double s_H[RZ][PS];              // flux at the upper edge of the row's zone
@@ -245,6 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         __syncthreads();                                    // previous chunk done with the LDS rows
         if (tile) {
             s_psi[zl][k] = p;
+            if (nes) s_pq[zl][k] = make_double2(p, 1.0 - p);
             s_lam[zl][k] = lam;
         }
         if (t < 3 * RZ + 2) s_z[t] = cur.zv;
@@ -320,29 +322,36 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         double S = 0.0;
         if (nes) {
             const double amp = s_amp[zl];
-            double sin_ = 0.0, sout = 0.0, e = 1.0;
-            // k' > k: the out kernel carries exp(-(eps_k' - eps_k)/T) = prod_{j=k}^{k'-1} d_j
+            // k' > k: the out kernel carries exp(-(eps_k' - eps_k)/T) = prod_{j=k}^{k'-1} d_j.  The weighted sum
+            // of those products is taken in Horner form from the last group down, one multiply-add and one
+            // multiply per term: h <- (h + P_kk' (1 - psi_k')) d_{k'-1}.
+            // the group index through an opaque copy: the lane masks of the two loops are then formed here
+            // (one compare per term) instead of being hoisted out of the zone loop as 38 live scalar masks
+            int kz = k;
+            asm volatile("" : "+v"(kz));
+            double hup = 0.0, sin_ = 0.0;
 #pragma unroll
-            for (int kp = 1; kp < NT; ++kp) {
-                if (kp >= N) break;
-                if (kp > k) {
-                    const double Pk = s_P[k * PS + kp], pp = s_psi[zl][kp];
-                    e *= s_d[zl][kp - 1];
-                    sout = fma(Pk * e, 1.0 - pp, sout);
-                    sin_ = fma(Pk, pp, sin_);
+            for (int kp = NT - 1; kp >= 1; --kp) {
+                if (kp > kz) {                         // padding groups add exact zeros (P = 0 there)
+                    const double Pk = s_P[k * PS + kp];
+                    const double2 pq = s_pq[zl][kp];
+                    hup = fma(Pk, pq.y, hup) * s_d[zl][kp - 1];
+                    sin_ = fma(Pk, pq.x, sin_);
                 }
             }
-            // k' < k: the in kernel carries exp(-(eps_k - eps_k')/T) = prod_{j=k'}^{k-1} d_j
-            e = 1.0;
+            // k' < k: the in kernel carries exp(-(eps_k - eps_k')/T) = prod_{j=k'}^{k-1} d_j, in Horner form from
+            // group 0 up: h <- (h + P_kk' psi_k') d_k'
+            double hdn = 0.0, sout = hup;
 #pragma unroll
-            for (int kp = NT - 2; kp >= 0; --kp) {
-                if (kp < k) {
-                    const double Pk = s_P[k * PS + kp], pp = s_psi[zl][kp];
-                    e *= s_d[zl][kp];
-                    sin_ = fma(Pk * e, pp, sin_);
-                    sout = fma(Pk, 1.0 - pp, sout);
+            for (int kp = 0; kp < NT - 1; ++kp) {
+                if (kp < kz) {
+                    const double Pk = s_P[k * PS + kp];
+                    const double2 pq = s_pq[zl][kp];
+                    hdn = fma(Pk, pq.x, hdn) * s_d[zl][kp];
+                    sout = fma(Pk, pq.y, sout);
                 }
             }
+            sin_ += hdn;
             S = amp * ((1.0 - p) * sin_ - p * sout);
             G -= c * S;
             scale += c * amp * (fabs(1.0 - p) * fabs(sin_) + fabs(p) * fabs(sout));

@@ -242,6 +242,9 @@ __device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, b
     int lo = lane;
     asm volatile("" : "+v"(lo));
     const int ta = lo >> 3, tb = lo & 7;
+    // growth guard: at every step each lane checks one multiplier, entry T ta + (tb mod T) of the pivot
+    // column, so the eight lanes of a tile row cover its T rows and the wavefront covers the column
+    const int gs = T * ta + tb % T;
     double t[T][T];
     double gmax = 0.0;
 #pragma unroll
@@ -263,9 +266,9 @@ __device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, b
 #pragma unroll
             for (int tc = 0; tc < T; ++tc) ur[T * tb + tc] = t[rp][tc];
         }
-        if (tb == ap) {
+        if (tb == ap) {                                // the pivot itself goes in as 0: its row's multiplier
 #pragma unroll
-            for (int tr = 0; tr < T; ++tr) uc[T * ta + tr] = t[tr][rp];
+            for (int tr = 0; tr < T; ++tr) uc[T * ta + tr] = (tr == rp && ta == ap) ? 0.0 : t[tr][rp];
         }
         wave_sync();
         const double piv = ur[cc], bpiv = L.bpv[cc];
@@ -275,11 +278,8 @@ __device__ __forceinline__ void tile_eliminate(Lds& L, int lane, double limit, b
 #pragma unroll
         for (int tc = 0; tc < T; ++tc) u[tc] = ur[T * tb + tc];
 #pragma unroll
-        for (int tr = 0; tr < T; ++tr) {
-            nf[tr] = uc[T * ta + tr] * npinv;
-            if (tr == rp && ta == ap) nf[tr] = 0.0;    // the pivot row itself
-            gmax = fmax(gmax, fabs(nf[tr]));
-        }
+        for (int tr = 0; tr < T; ++tr) nf[tr] = uc[T * ta + tr] * npinv;   // 0 for the pivot row itself
+        gmax = fmax(gmax, fabs(uc[gs] * npinv));
 #pragma unroll
         for (int tr = 0; tr < T; ++tr)
 #pragma unroll

@@ -322,13 +322,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(Shape sh, Fields f, const C
         double S = 0.0;
         if (nes) {
             const double amp = s_amp[zl];
+            // The group index goes through an opaque copy: the lane masks of the two loops are then formed here
+            // (one compare per term) instead of being hoisted out of the zone loop as 38 live scalar masks.
+            int kz = k;
+            asm volatile("" : "+v"(kz));
             // k' > k: the out kernel carries exp(-(eps_k' - eps_k)/T) = prod_{j=k}^{k'-1} d_j.  The weighted sum
             // of those products is taken in Horner form from the last group down, one multiply-add and one
             // multiply per term: h <- (h + P_kk' (1 - psi_k')) d_{k'-1}.
-            // the group index through an opaque copy: the lane masks of the two loops are then formed here
-            // (one compare per term) instead of being hoisted out of the zone loop as 38 live scalar masks
-            int kz = k;
-            asm volatile("" : "+v"(kz));
             double hup = 0.0, sin_ = 0.0;
 #pragma unroll
             for (int kp = NT - 1; kp >= 1; --kp) {

@@ -520,10 +520,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
                 double v = -bm * frow[m];
                 if (m < NT) v += q0 ? nrow[m] : 0.0;
                 else if (m < NC) v += q0 ? 0.0 : nrow[m - NT];
-                v += (m == lz) ? diag : 0.0;
                 if (m == NC) v += ycol;
                 frow[m] = v;
             }
+            frow[lz] += diag;                          // once, at the lane's own column (not a select per column)
         } else if (lane < NC) {
 #pragma unroll
             for (int m = 0; m < MT; ++m) frow[m] = (m == lz) ? 1.0 : 0.0;     // padded identity row

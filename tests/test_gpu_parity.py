@@ -85,6 +85,43 @@ def test_residual_and_blocks_match_oracle(shape):
             np.testing.assert_allclose(B[s, r, :, :, w.N + 1], bp, rtol=1e-11, atol=1e-14 * scale.max())
 
 
+# Temperature scaled far below and above the synthetic profile (eq. d8's detailed-balance factor
+# exp(-|eps_k - eps_k'|/T)): cold zones make the factors of distant groups underflow to 0, hot zones
+# bring every factor near 1.  The residual's NES sums (products of neighbour factors, summed from the far
+# end) must match the oracle, which takes each factor directly; there the NES amplitude is raised 1e5-fold
+# so that the NES source dominates the residual (about 1e4 times the rest).  The Newton steps run at 10
+# times the synthetic amplitude (NES about as large as the rest), where diagonal pivoting holds (no
+# fallback), so the float32 NES block of the mixed update (one exp2 per entry, weights split by side)
+# does the solves.
+@pytest.mark.parametrize("t_scale", [0.02, 50.0])
+def test_nes_at_extreme_temperatures_matches_oracle(t_scale):
+    say("case NES extreme temperature", t_scale)
+    base = synth.make_custom(S=2, R=4, I=24, N=20)
+    w = dataclasses.replace(base, temp=(base.temp * t_scale).contiguous(), nes_amp=(base.nes_amp * 1e5).contiguous())
+    rng = np.random.default_rng(5)
+    psi = (w.psi_n.numpy() * rng.uniform(0.7, 1.3, w.psi_n.shape)).clip(0, 1)
+    wd = w.to("cuda")
+    ctx, f = _ctx(wd)
+    psi_d = torch.as_tensor(psi, device="cuda")
+    G = torch.empty_like(psi_d)
+    ctx.assemble(f, wd.psi_n, psi_d, G, None)
+    torch.cuda.synchronize()
+    G = G.cpu().numpy()
+    wn = w.numpy()
+    syss = oracle.systems_from_workload(wn)
+    for s in range(w.S):
+        for r in range(w.R):
+            Go = oracle.residual(syss[s][r], wn["psi_n"][s, r], psi[s, r])
+            np.testing.assert_allclose(G[s, r], Go, rtol=1e-11, atol=1e-13)
+    w = dataclasses.replace(base, temp=(base.temp * t_scale).contiguous(), nes_amp=(base.nes_amp * 10.0).contiguous())
+    ref, _ = oracle_newton(w, 30, 1e-12)
+    for precision, bar in [(tm.PREC_FP64, FP64_BAR), (tm.PREC_MIXED, MIXED_BAR)]:
+        st, psi_m, stats = gpu_newton(w, 30, 1e-12, precision=precision)
+        assert st == 0, tm.STATUS_NAMES[st]
+        assert not np.any(stats["flags"] & tm.FLAG_PIVOT_FALLBACK)
+        assert rel_err(psi_m, ref) < bar
+
+
 # ------------------------------------------------------------------ linear solves
 
 @pytest.mark.parametrize("transpose", [False, True])

@@ -148,9 +148,10 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 constexpr int kQuadBlock = 64;          // one wavefront per workgroup
 constexpr int kQuadSystems = 16;        // systems per wavefront
 
-// Workspace of the quad kernel, per wave group of 16 systems and zone: C as R * NT runs of 64 floats
-// (entry j of lane l's row slot s at [s NT + j][l]), then y as R runs of 64 floats.  A group takes
-// 16 * NT * (NT + 1) floats per zone, the same as 16 slots of the one-row-per-lane layout.
+// Workspace of the quad kernel, per wave group of 16 systems and zone: C as R * NT/4 runs of 64 float4
+// (entries 4t .. 4t+3 of lane l's row slot s at [s NT/4 + t][l], one 16-byte store or load per lane and
+// run), then y as R runs of 64 floats.  A group takes 16 * NT * (NT + 1) floats per zone, the same as 16
+// slots of the one-row-per-lane layout.
 // Splits x into bf16 parts: x = hi + lo up to 2^-17 |x| (NB = 3), or hi alone (NB = 1).  The matrix-core
 // products from the parts are hi hi (NB = 1), or hi hi + hi lo + lo hi (NB = 3, about float32 accuracy:
 // the lo lo term is below 2^-16 relative).
@@ -723,7 +724,7 @@ void k_factor_q(FactorArgs A) {
 #pragma unroll
             for (int s = 0; s < R; ++s)
 #pragma unroll
-                for (int j = 0; j < NT; ++j) st_nt(qc + (s * NT + j) * 64, wl1, AE(s, j));
+                for (int t = 0; t < NT / 4; ++t) st_nt(reinterpret_cast<v4f*>(qc) + (s * (NT / 4) + t) * 64, 4u * wl1, a4[s][t]);
             float* qy = uniform_ptr(wsY + (size_t)i * kQuadSystems * NT);
 #pragma unroll
             for (int s = 0; s < R; ++s) st_nt(qy + s * 64, wl1, g[s]);
@@ -752,7 +753,8 @@ void k_factor_q(FactorArgs A) {
     // pipelined like the forward sweep: zone i-1's factors (and, for a Newton update, its psi) are loaded
     // before zone i's back substitution and output stores
     struct Behind {
-        float c[R][NT], y[R];
+        v4f c[R][NT / 4];
+        float y[R];
         double ps[R];
     };
     auto fetch_back = [&](int z) {
@@ -765,7 +767,7 @@ void k_factor_q(FactorArgs A) {
         for (int s = 0; s < R; ++s) {
             b.y[s] = ld_nt(qy + s * 64, gz.wl);
 #pragma unroll
-            for (int j = 0; j < NT; ++j) b.c[s][j] = ld_nt(qc + (s * NT + j) * 64, gz.wl);
+            for (int t = 0; t < NT / 4; ++t) b.c[s][t] = ld_nt(reinterpret_cast<const v4f*>(qc) + (s * (NT / 4) + t) * 64, 4u * gz.wl);
             const int k = 4 * s + gz.q;
             b.ps[s] = pz ? at(pz, k < N ? gz.lb + 32u * s : gz.lb - 8u * gz.q) : 0.0;
         }
@@ -789,7 +791,7 @@ void k_factor_q(FactorArgs A) {
             for (int m = 0; m < NT; ++m) {
                 const float xm = qbc(dn[m / 4], m % 4);
 #pragma unroll
-                for (int s = 0; s < R; ++s) dl[s] = fmaf(-bh.c[s][m], xm, dl[s]);
+                for (int s = 0; s < R; ++s) dl[s] = fmaf(-bh.c[s][m / 4][m % 4], xm, dl[s]);
             }
         }
         if (store_out) {

@@ -413,6 +413,16 @@ typedef struct {
 tm_status tm_energy_advect(tm_ctx *ctx, const tm_inputs *in, const tm_eadv_inputs *ea, double *psi,
                            double *xi, int32_t *flags);
 
+/* Kernel timing, a measurement aid (not an operation of the method): for benchmarks that relate the
+ * diagonal-pivot factor kernel to its roofline.  With timing enabled, tm_factor_solve and tm_newton_step
+ * bracket their diagonal-pivot factor launch(es) (all batches, nothing else in between) with two HIP
+ * events on the context's stream.  tm_kernel_time_ms waits for the second event of the last bracketed
+ * call and writes the elapsed milliseconds to *ms (host pointer); TM_ERR_INVALID_ARG when timing is off,
+ * ms is NULL or no call has been bracketed since it was enabled.  Enabling creates the two events (once
+ * per context; released by tm_destroy); disabling keeps them.                                          */
+tm_status tm_set_kernel_timing(tm_ctx *ctx, int32_t enable);
+tm_status tm_kernel_time_ms(tm_ctx *ctx, double *ms);
+
 /* Human-readable name of a status code (static storage).                          */
 const char *tm_status_string(tm_status status);
 

@@ -48,6 +48,10 @@ struct tm_ctx {
     int factor_kernel = tmk::kFactorQuadMfma;   // float32 diagonal-pivot solve: TM_FACTOR_KERNEL=window|bf16x3|bf16|mfma|valu|lane
     double growth_limit = 16.0;
     long long pivot_fallbacks = 0;   // systems re-factored with partial pivoting since creation
+    // kernel timing (measurement aid): events around the diagonal-pivot factor launches
+    hipEvent_t kt[2] = {nullptr, nullptr};
+    bool timing = false;
+    bool timed = false;                 // an enabled call has recorded both events
     // Y_e-coupled step, per ray [R] unless stated (allocated on first use)
     double* y_res = nullptr;
     double* y_res0 = nullptr;
@@ -352,10 +356,15 @@ tm_status run_factor(tm_ctx* c, const tm_inputs* in, const double* psi, const do
     const bool pivot_first = c->pivot_policy == 1;
     if (!pivot_first)
         TM_TRY(hip_check(c, hipMemsetAsync(c->guard, 0, ns * sizeof(int), c->stream), "memset guard"));
+    if (c->timing) TM_TRY(hip_check(c, hipEventRecord(c->kt[0], c->stream), "timing event"));
     for (long long s0 = 0; s0 < ns; s0 += batch) {
         a.sys0 = s0;
         a.nsys = std::min(batch, ns - s0);
         TM_TRY(hip_check(c, tmk::launch_factor(a, fp32, transpose, pivot_first, c->stream, c->factor_kernel), "factor kernel"));
+    }
+    if (c->timing) {
+        TM_TRY(hip_check(c, hipEventRecord(c->kt[1], c->stream), "timing event"));
+        c->timed = true;
     }
     if (pivot_first) return TM_OK;
     // systems whose diagonal-pivot elimination tripped the growth guard were left untouched:
@@ -467,6 +476,28 @@ const char* tm_status_string(tm_status s) {
 
 const char* tm_last_error(const tm_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
 
+tm_status tm_set_kernel_timing(tm_ctx* c, int32_t enable) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if (enable && !c->kt[0]) {
+        TM_TRY(hip_check(c, hipSetDevice(c->device), "set device"));
+        for (hipEvent_t& e : c->kt) TM_TRY(hip_check(c, hipEventCreate(&e), "create timing event"));
+    }
+    c->timing = enable != 0;
+    c->timed = false;
+    return TM_OK;
+}
+
+tm_status tm_kernel_time_ms(tm_ctx* c, double* ms) {
+    if (!c) return TM_ERR_INVALID_ARG;
+    if (!ms || !c->timing || !c->timed)
+        return set_err(c, TM_ERR_INVALID_ARG, "kernel timing needs timing enabled, ms and a timed call");
+    TM_TRY(hip_check(c, hipEventSynchronize(c->kt[1]), "timing event sync"));
+    float f = 0.0f;
+    TM_TRY(hip_check(c, hipEventElapsedTime(&f, c->kt[0], c->kt[1]), "timing event elapsed"));
+    *ms = f;
+    return TM_OK;
+}
+
 size_t tm_workspace_bytes(const tm_problem* p, int64_t batch_systems) {
     if (!valid_problem(p, nullptr) || batch_systems < 0) return 0;
     const long long ns = n_systems(*p);
@@ -537,6 +568,8 @@ tm_status tm_destroy(tm_ctx* c) {
     if (c->gbuf) (void)hipFree(c->gbuf);
     if (c->dbuf) (void)hipFree(c->dbuf);
     if (c->ws && c->ws_owned) (void)hipFree(c->ws);
+    for (hipEvent_t e : c->kt)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return TM_OK;
 }

@@ -29,7 +29,8 @@ EADV_FLAG_DISPLACEMENT, EADV_FLAG_OVERFILL, EADV_FLAG_OVERFILL_CLAMP = 1, 2, 4
 
 EXPORTED = ["tm_create", "tm_destroy", "tm_workspace_bytes", "tm_set_workspace", "tm_assemble",
             "tm_factor_solve", "tm_factor_solve_noalloc", "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_workspace_bytes",
-            "tm_ye_newton_step", "tm_temperature_update", "tm_energy_advect", "tm_status_string", "tm_last_error"]
+            "tm_ye_newton_step", "tm_temperature_update", "tm_energy_advect", "tm_set_kernel_timing",
+            "tm_kernel_time_ms", "tm_status_string", "tm_last_error"]
 
 
 class TMError(RuntimeError):
@@ -99,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tm_ye_newton_step.argtypes = [V, P(Inputs), P(YeInputs), V, V, V, I32, D, P(YeStats)]
     lib.tm_temperature_update.argtypes = [V, P(Inputs), P(YeInputs), V, V, P(D), V, V, V, V]
     lib.tm_energy_advect.argtypes = [V, P(Inputs), P(EadvInputs), V, V, V]
+    lib.tm_set_kernel_timing.argtypes = [V, I32]
+    lib.tm_kernel_time_ms.argtypes = [V, P(D)]
     lib.tm_status_string.argtypes = [ctypes.c_int]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = [V]
@@ -106,7 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("tm_create", "tm_destroy", "tm_set_workspace", "tm_assemble", "tm_factor_solve",
                  "tm_factor_solve_noalloc",
                  "tm_newton_step", "tm_adjoint_step", "tm_luminosity_seed", "tm_ye_newton_step",
-                 "tm_temperature_update", "tm_energy_advect"):
+                 "tm_temperature_update", "tm_energy_advect", "tm_set_kernel_timing", "tm_kernel_time_ms"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -245,6 +248,16 @@ class Context:
         inp = self._inputs(f)
         self._check(self.lib.tm_factor_solve(self._h, ctypes.byref(inp), _ptr(psi), _ptr(rhs), _ptr(x),
                                              int(bool(transpose))))
+
+    def set_kernel_timing(self, enable: bool):
+        """Bracket the diagonal-pivot factor launches of later solves with HIP events (measurement aid)."""
+        self._check(self.lib.tm_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_time_ms(self) -> float:
+        """Milliseconds between the events of the last bracketed factor launch (waits for it)."""
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.tm_kernel_time_ms(self._h, ctypes.byref(ms)))
+        return ms.value
 
     def factor_solve_noalloc(self, f: DeviceFields, psi, rhs, x, transpose=False, flags=None):
         """tm_factor_solve_noalloc: the solve with the library's static scratch (no allocation, no

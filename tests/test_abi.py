@@ -118,3 +118,10 @@ def test_ye_entry_points_reject_a_null_context():
 def test_energy_advect_rejects_a_null_context():
     lib = tm.load_library()
     assert lib.tm_energy_advect(None, None, None, None, None, None) == 1
+
+
+def test_kernel_timing_rejects_a_null_context():
+    lib = tm.load_library()
+    ms = ctypes.c_double(0.0)
+    assert lib.tm_set_kernel_timing(None, 1) == 1
+    assert lib.tm_kernel_time_ms(None, ctypes.byref(ms)) == 1

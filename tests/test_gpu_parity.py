@@ -122,6 +122,30 @@ def test_nes_at_extreme_temperatures_matches_oracle(t_scale):
         assert rel_err(psi_m, ref) < bar
 
 
+def test_kernel_timing_brackets_the_factor_launch():
+    """The measurement aid: with timing on, a solve records two events around its factor launch; off (or
+    before any timed call) the query is an invalid argument."""
+    say("case kernel timing")
+    w = synth.make_custom(S=2, R=8, I=40, N=12)
+    wd = w.to("cuda")
+    for precision in (tm.PREC_FP64, tm.PREC_MIXED):
+        ctx, f = _ctx(wd, precision)
+        rhs = torch.ones_like(wd.psi_n)
+        x = torch.empty_like(rhs)
+        with pytest.raises(tm.TMError, match="INVALID_ARG"):
+            ctx.kernel_time_ms()
+        ctx.set_kernel_timing(True)
+        with pytest.raises(tm.TMError, match="INVALID_ARG"):
+            ctx.kernel_time_ms()
+        ctx.factor_solve(f, wd.psi_n, rhs, x)
+        ms = ctx.kernel_time_ms()
+        assert 0.0 < ms < 1e4
+        ctx.set_kernel_timing(False)
+        with pytest.raises(tm.TMError, match="INVALID_ARG"):
+            ctx.kernel_time_ms()
+        ctx.close()
+
+
 # ------------------------------------------------------------------ linear solves
 
 @pytest.mark.parametrize("transpose", [False, True])

@@ -184,7 +184,8 @@ tm_status tm_destroy(tm_ctx *ctx);
 size_t tm_workspace_bytes(const tm_problem *problem, int64_t batch_systems);
 
 /* Hand the context caller-owned device workspace (>= tm_workspace_bytes(p, b) or
- * tm_ye_workspace_bytes(p, b) for some batch b >= 1, else TM_ERR_WORKSPACE); the context
+ * tm_ye_workspace_bytes(p, b) for some batch b >= 1, else TM_ERR_WORKSPACE; 256-byte
+ * aligned, as device allocations are, else TM_ERR_INVALID_ARG); the context
  * then launches the factorisation in batches that fit.  A step whose own need for one
  * batch exceeds the workspace returns TM_ERR_WORKSPACE.  Without it, the context
  * allocates workspace for all systems on first use.  Pass NULL/0 to go back to
@@ -323,7 +324,8 @@ typedef struct {             /* every array is per ray [R], device memory       
 } tm_ye_stats;
 
 /* Device bytes of workspace needed to factor `batch_rays` coupled systems per launch
- * (0 means all R): b slots of I*(2NT+1)^2 doubles (NT = N padded to a multiple of 4).
+ * (0 means all R): b slots of I*((2NT+1)^2 + 1) doubles (NT = N padded to a multiple of
+ * 4; per zone C, y and one pad double).
  * Returns 0 for an invalid problem or N > 28.  A workspace given with
  * tm_set_workspace serves both steps; the coupled step then runs in batches of
  * floor(bytes / slot) rays.                                                          */

@@ -578,6 +578,8 @@ tm_status tm_set_workspace(tm_ctx* c, void* dev, size_t bytes) {
     if (!c) return TM_ERR_INVALID_ARG;
     if ((dev == nullptr) != (bytes == 0))
         return set_err(c, TM_ERR_INVALID_ARG, "workspace pointer and size must both be set or both be 0");
+    if (reinterpret_cast<uintptr_t>(dev) % 256 != 0)   // the factor kernels store 16-byte vectors into it
+        return set_err(c, TM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (dev) {
         // enough for one launch of either step (each step checks its own need when it runs)
         const size_t one_sys = (size_t)(1 + tmk::kWsPadSystems) *

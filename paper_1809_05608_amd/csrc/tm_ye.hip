@@ -221,6 +221,36 @@ __device__ __forceinline__ double lane_value(double v, int p) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// One zone's slot of the coupled factor workspace: C_i's row of lane l (NC values) as NC/2 runs of MT
+// pairs, pair j at [j MT + l], then y_i at [NC MT + l].  The slot stride is rounded up to an even number
+// of doubles so that every pair is 16-byte aligned.
+typedef double yd2 __attribute__((ext_vector_type(2)));
+template <int NT>
+constexpr size_t ye_slot_doubles() {
+    constexpr size_t n = (size_t)(2 * NT + 1) * (2 * NT + 1);
+    return n + (n & 1);
+}
+template <int NC, int MT>
+__device__ __forceinline__ void store_slot(double* slot, int lane, const double* row, double y) {
+#pragma unroll
+    for (int j = 0; j < NC / 2; ++j) {
+        const yd2 v = {row[2 * j], row[2 * j + 1]};
+        nt_store(reinterpret_cast<yd2*>(slot) + (size_t)j * MT + lane, v);
+    }
+    nt_store(slot + (size_t)NC * MT + lane, y);
+}
+template <int NC, int MT>
+__device__ __forceinline__ void load_slot(const double* slot, int lane, bool ok, double (&c)[NC], double& y) {
+#pragma unroll
+    for (int j = 0; j < NC / 2; ++j) {
+        const yd2 v = nt_load(reinterpret_cast<const yd2*>(slot) + (size_t)j * MT + lane);
+        c[2 * j] = ok ? v.x : 0.0;
+        c[2 * j + 1] = ok ? v.y : 0.0;
+    }
+    const double yy = nt_load(slot + (size_t)NC * MT + lane);
+    y = ok ? yy : 0.0;
+}
+
 // waves per SIMD the register allocation is held to: two up to 20 groups (256 VGPRs, no scratch), one above
 template <int NT>
 constexpr int ye_waves_per_eu() { return NT <= 20 ? 2 : 1; }
@@ -365,7 +395,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     const double c = sh.c_dt;
     const double Wk = real ? A.cs->W[kk] : 0.0;
     const double* Prow = s_P + kk * PS;
-    double* ws = A.ws + (size_t)rb * I * (NC + 1) * MT;                // zone i: C [NC][MT], then y [MT]
+    // zone i's slot, ye_slot_doubles(NT) doubles (16-byte aligned): C as NC/2 runs of MT pairs (columns
+    // 2j, 2j+1 of lane l at pair j MT + l, one 16-byte store or load per lane and run), then y [MT]
+    constexpr size_t SZ = ye_slot_doubles<NT>();
+    double* ws = A.ws + (size_t)rb * I * SZ;
 
     // ---------------------------------------------------------------- forward sweep
     // L.fix holds, between zones, the rows of C_{i-1} (columns [0, MT)) and y_{i-1} (column MT) in natural
@@ -385,7 +418,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     if (nes && lane < NT) {
         const double dej = lane + 1 < N ? A.cs->de[lane] : 0.0;
         for (int i = 0; i < I; ++i)
-            ws[(size_t)i * (NC + 1) * MT + lane] = (lane + 1 < N) ? exp(-dej / tz[i]) : 0.0;
+            ws[(size_t)i * SZ + lane] = (lane + 1 < N) ? exp(-dej / tz[i]) : 0.0;
     }
     double psi_c = real ? psi[kk] : 0.0;
     double sig_c = real ? ka[kk] + et[kk] : 0.0;
@@ -461,7 +494,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         const bool pair = EXT && A.y.pair_amp != nullptr;
         if (nes) {
             amp = az[i];
-            if (lane < NT) L.dd[lane] = ws[(size_t)i * (NC + 1) * MT + lane];
+            if (lane < NT) L.dd[lane] = ws[(size_t)i * SZ + lane];
         }
         if (nes || pair) {
             if (lane < NC) L.bc[lane] = real ? psi_c : 0.0;
@@ -508,10 +541,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         if (is_row) {
             ycar = frow[MT];
             if (i > 0) {                               // C_{i-1}, y_{i-1} to the workspace
-                double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + lane;
-#pragma unroll
-                for (int m = 0; m < NC; ++m) nt_store(wz + (size_t)m * MT, frow[m]);
-                nt_store(wz + (size_t)NC * MT, ycar);
+                store_slot<NC, MT>(ws + (size_t)(i - 1) * SZ, lane, frow, ycar);
             }
         }
         if (real) {
@@ -632,10 +662,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
         if (bad) return;
     }
     if (is_row) {                                      // C_{I-1}, y_{I-1}
-        double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + lane;
-#pragma unroll
-        for (int m = 0; m < NC; ++m) nt_store(wz + (size_t)m * MT, frow[m]);
-        nt_store(wz + (size_t)NC * MT, frow[MT]);
+        store_slot<NC, MT>(ws + (size_t)(I - 1) * SZ, lane, frow, frow[MT]);
     }
 
     // ---------------------------------------------------------------- backward sweep
@@ -649,20 +676,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
     const size_t cellb = ((size_t)(realb ? qb : 0) * R + ray) * I * N + (realb ? kgb : 0);
     double cr[NC], crn[NC];
     double yv = 0.0, yn = 0.0;
-    {
-        const double* wz = ws + (size_t)(I - 1) * (NC + 1) * MT + kb;
-#pragma unroll
-        for (int m = 0; m < NC; ++m) cr[m] = is_row ? nt_load(wz + (size_t)m * MT) : 0.0;
-        yv = is_row ? nt_load(wz + (size_t)NC * MT) : 0.0;
-    }
+    load_slot<NC, MT>(ws + (size_t)(I - 1) * SZ, kb, is_row, cr, yv);
     double dnext = 0.0;
     for (int i = I - 1; i >= 0; --i) {
-        if (i > 0) {
-            const double* wz = ws + (size_t)(i - 1) * (NC + 1) * MT + kb;
-#pragma unroll
-            for (int m = 0; m < NC; ++m) crn[m] = is_row ? nt_load(wz + (size_t)m * MT) : 0.0;
-            yn = is_row ? nt_load(wz + (size_t)NC * MT) : 0.0;
-        }
+        if (i > 0) load_slot<NC, MT>(ws + (size_t)(i - 1) * SZ, kb, is_row, crn, yn);
         double dl = yv;
         if (i + 1 < I) {
             if (lane < NC) L.bc[lane] = dnext;
@@ -696,8 +713,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEU))) v
 size_t ye_ws_bytes_per_ray(int I, int N) {
     const int NT = padded_groups(N);
     if (NT < 0 || N > kYeMaxGroups) return 0;
-    const size_t MT = 2 * NT + 1;
-    return (size_t)I * MT * MT * sizeof(double);     // per zone: C [2 NT][MT] and y [MT]
+    const size_t n = (size_t)(2 * NT + 1) * (2 * NT + 1);   // per zone: C [2 NT][MT] and y [MT] ...
+    return (size_t)I * (n + (n & 1)) * sizeof(double);     // ... rounded up to an even count (16-byte slots)
 }
 
 // ---------------------------------------------------------------- line-search move-back

@@ -73,7 +73,7 @@ int main(void) {
     CHECK(tm_workspace_bytes(&p, 0) == (size_t)(40 + 15) * 540 * 20 * 21 * 8);
     CHECK(tm_workspace_bytes(&p, 3) == (size_t)(3 + 15) * 540 * 20 * 21 * 8);
     CHECK(tm_workspace_bytes(&p, -1) == 0);
-    CHECK(tm_ye_workspace_bytes(&p, 0) == (size_t)10 * 540 * 41 * 41 * 8);
+    CHECK(tm_ye_workspace_bytes(&p, 0) == (size_t)10 * 540 * (41 * 41 + 1) * 8);
     tm_problem pm = base_problem();
     pm.n_groups = 13;
     pm.precision = TM_PREC_MIXED;

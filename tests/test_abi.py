@@ -97,14 +97,15 @@ def test_null_context_is_an_error():
 
 
 def test_ye_workspace_bytes_formula():
-    """The coupled step keeps, per ray and zone, C [2NT][2NT+1] and y [2NT+1] in float64."""
+    """The coupled step keeps, per ray and zone, C [2NT][2NT+1] and y [2NT+1] in float64, padded by one
+    double to an even count (16-byte aligned slots)."""
     lib = tm.load_library()
     p = _prob(S=4, R=10, I=540, N=20)
-    per = 540 * 41 * 41 * 8
+    per = 540 * (41 * 41 + 1) * 8
     assert lib.tm_ye_workspace_bytes(ctypes.byref(p), 0) == 10 * per
     assert lib.tm_ye_workspace_bytes(ctypes.byref(p), 3) == 3 * per
     p13 = _prob(S=2, R=10, I=7, N=13)                  # padded to 16 groups: blocks of 33
-    assert lib.tm_ye_workspace_bytes(ctypes.byref(p13), 1) == 7 * 33 * 33 * 8
+    assert lib.tm_ye_workspace_bytes(ctypes.byref(p13), 1) == 7 * (33 * 33 + 1) * 8
     assert lib.tm_ye_workspace_bytes(ctypes.byref(_prob(N=29)), 0) == 0     # 2 NT + 1 rows exceed a wavefront
     assert lib.tm_ye_workspace_bytes(ctypes.byref(p), -1) == 0
 

@@ -21,7 +21,7 @@ common factor 4 pi (eq. p4).
 
 Only `tests/` may import this module.  It shares no code with the HIP path.
 
-Readings (the paper is silent, garbled or inconsistent here; each is listed in the design doc):
+Readings (the paper is silent, garbled or inconsistent here):
   * PPM variable and geometry: the zone average is a_k = N_k / dE_k (proportional to
     eps_k^2 psi_k by eq. a01b) on the energy coordinate, with the planar (phi-direction) forms of
     eqs. h6-h14 and h24 (dV/dxi = 1, a* = a);

@@ -17,7 +17,7 @@ unknowns are psi^{n+1}_{i,k}; the residual is c*dt times eq. a58 with the
 source of eq. a54 (emission/absorption with Pauli blocking) and the zeroth
 moment of eq. d8 / eq. d40 (inelastic NES-like scattering, Phi_0 terms).
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
   * eq. a01 prints eps_k instead of eps_k^2 on the left; the square is restored
     so that eq. a01b holds.
   * the limiter's psi in eq. a20 is the edge mean (psi_i + psi_{i+1})/2, floored

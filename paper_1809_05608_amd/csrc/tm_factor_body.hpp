@@ -138,19 +138,33 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     const double* tz = A.f.temp + (size_t)ray * I;
     const double c = sh.c_dt;
     const bool diff = sh.terms & kDiffusion, emabs = sh.terms & kEmAbs, nes = sh.terms & kNes;
-    // Workspace, interleaved by wave group: the SPW systems of group g keep, per zone i and column m,
-    // one run of SPW * NT values, system s at offset s * NT and row k at s * NT + k.  A wave's store or
-    // load of column m is then one contiguous run (3 * 20 floats at N = 20) rather than SPW separate
-    // pieces.  A last partial group has empty slots, which the workspace size allows for
+    // Workspace, interleaved by wave group: the SPW systems of group g keep, per zone i and column m
+    // (column pair for FP64), one run of SPW * NT entries, system s at offset s * NT and row k at
+    // s * NT + k.  A wave's store or load of a column is then one contiguous run (3 * 20 entries at
+    // N = 20) rather than SPW separate pieces.  A last partial group has empty slots, which the workspace size allows for
     // (kWsPadSystems); lanes of a clamped system use that system's slot.
     // sbc / SPW, the same for every lane of the wave (a clamped lane's system is the batch's last, which lies
     // in this wave whenever any lane of it is live), so the workspace bases stay scalar
     const long long wg = (long long)blockIdx.x * (SPB / SPW) + wave;
     const int lo = (int)(sbc - wg * SPW) * NT + k;             // this lane's place in a run
-    constexpr int zs = SPW * NT;                                // values per (zone, column) run
+    constexpr int zs = SPW * NT;                                // entries per (zone, column) run
     T* wsC = reinterpret_cast<T*>(A.wsC) + (size_t)wg * SPW * I * NT * NT;
     T* wsY = reinterpret_cast<T*>(A.wsY) + (size_t)wg * SPW * I * NT;
     const bool store = live && real;
+    // FP64 rows go as column pairs (16 bytes per lane and instruction): run j of a zone holds columns
+    // 2j, 2j+1 of every row as pairs.  Float32 rows keep one column per run (pairs spill the 5-wave kernel).
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    constexpr bool PAIRS = sizeof(T) == 8;
+    // FP64 row of zone z as this lane stored it (columns at or beyond N, or !ok, read as 0); nt: non-temporal
+    auto ws_row = [&](int z, bool ok, bool nt, T (&c)[NT]) {
+        const V2* q = reinterpret_cast<const V2*>(wsC + (size_t)z * NT * zs) + lo;
+#pragma unroll
+        for (int j = 0; j < NT / 2; ++j) {
+            const V2 v = (ok && 2 * j < N) ? (nt ? nt_load(q + (size_t)j * zs) : q[(size_t)j * zs]) : V2{(T)0, (T)0};
+            c[2 * j] = v.x;
+            c[2 * j + 1] = 2 * j + 1 < N ? v.y : (T)0;
+        }
+    };
 
     const T* Prow = s_P + kr * PS;                  // row k of the NES shape (zero outside N x N)
     const double de_k = A.cs->de[kp_safe];
@@ -345,11 +359,18 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
             // the previous factor row, as this lane stored it at the end of the previous zone (read back
             // rather than held in registers through the assembly)
             const T s = real ? (T)bp_prev : (T)0;
-            const T* qp = wsC + (size_t)(i > 0 ? i - 1 : 0) * NT * zs + lo;
+            if constexpr (PAIRS) {
+                T prev[NT];
+                ws_row(i > 0 ? i - 1 : 0, i > 0 && store, false, prev);
 #pragma unroll
-            for (int m = 0; m < NT; ++m) {
-                const T prev = (i > 0 && store && m < N) ? qp[(size_t)m * zs] : (T)0;
-                a[m] = fma(-s, prev, is_row ? L.fix[m][kr] : (T)0);
+                for (int m = 0; m < NT; ++m) a[m] = fma(-s, prev[m], is_row ? L.fix[m][kr] : (T)0);
+            } else {
+                const T* qp = wsC + (size_t)(i > 0 ? i - 1 : 0) * NT * zs + lo;
+#pragma unroll
+                for (int m = 0; m < NT; ++m) {
+                    const T prev = (i > 0 && store && m < N) ? qp[(size_t)m * zs] : (T)0;
+                    a[m] = fma(-s, prev, is_row ? L.fix[m][kr] : (T)0);
+                }
             }
             wave_sync();
             g = fma(-s, ycar, g);
@@ -449,13 +470,24 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
 
         if (store) {
             // non-temporal except where the transposed kernel reads the row back in the next zone
-            T* q = wsC + (size_t)i * NT * zs + lo;
+            if constexpr (PAIRS) {
+                V2* q = reinterpret_cast<V2*>(wsC + (size_t)i * NT * zs) + lo;
 #pragma unroll
-            for (int m = 0; m < NT; ++m)
-                if (m < N) {
-                    if (TRANS) q[(size_t)m * zs] = a[m];
-                    else nt_store(q + (size_t)m * zs, a[m]);
-                }
+                for (int j = 0; j < NT / 2; ++j)
+                    if (2 * j < N) {
+                        const V2 v = {a[2 * j], a[2 * j + 1]};
+                        if (TRANS) q[(size_t)j * zs] = v;
+                        else nt_store(q + (size_t)j * zs, v);
+                    }
+            } else {
+                T* q = wsC + (size_t)i * NT * zs + lo;
+#pragma unroll
+                for (int m = 0; m < NT; ++m)
+                    if (m < N) {
+                        if (TRANS) q[(size_t)m * zs] = a[m];
+                        else nt_store(q + (size_t)m * zs, a[m]);
+                    }
+            }
             nt_store(wsY + (size_t)i * zs + lo, ycar);
         }
 
@@ -499,18 +531,24 @@ __device__ __forceinline__ void factor_sweeps(const FactorArgs& A) {
     double* dxp = A.dx ? A.dx + cellb : nullptr;
     T cr[NT], crn[NT];
     T yv = (T)0, yn = (T)0;
-    {
+    if constexpr (PAIRS) {
+        ws_row(I - 1, real, true, cr);
+    } else {
         const T* q = wsC + (size_t)(I - 1) * NT * zs + lo;
 #pragma unroll
         for (int m = 0; m < NT; ++m) cr[m] = (real && m < N) ? nt_load(q + (size_t)m * zs) : (T)0;
-        yv = real ? nt_load(wsY + (size_t)(I - 1) * zs + lo) : (T)0;
     }
+    yv = real ? nt_load(wsY + (size_t)(I - 1) * zs + lo) : (T)0;
     T dnext = (T)0;
     for (int i = I - 1; i >= 0; --i) {
         if (i > 0) {
-            const T* q = wsC + (size_t)(i - 1) * NT * zs + lo;
+            if constexpr (PAIRS) {
+                ws_row(i - 1, real, true, crn);
+            } else {
+                const T* q = wsC + (size_t)(i - 1) * NT * zs + lo;
 #pragma unroll
-            for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? nt_load(q + (size_t)m * zs) : (T)0;
+                for (int m = 0; m < NT; ++m) crn[m] = (real && m < N) ? nt_load(q + (size_t)m * zs) : (T)0;
+            }
             yn = real ? nt_load(wsY + (size_t)(i - 1) * zs + lo) : (T)0;
         }
         T dl = yv;
